@@ -1,0 +1,216 @@
+/*
+ * pcr.h -- C ABI of libpcr, a compute point-cloud rasterizer for AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The operations follow Schuetz, Kerbl and Wimmer, "Rendering Point Clouds
+ * with Compute Shaders and Vertex Order Optimization" (EGSR 2021):
+ *   - closest-point rendering with one 64-bit atomic minimum per point on a
+ *     (depth, colour) key, and its resolve pass ............. Sec. 3.1
+ *   - the early depth test ................................... Sec. 3.2
+ *   - local reduction / deduplication of same-pixel updates .. Sec. 3.3, 3.4
+ *   - high-quality blending: depth pass, epsilon colour pass,
+ *     integer-average resolve ................................ Sec. 3.5
+ *   - Morton, shuffled-Morton and shuffled vertex orders ..... Sec. 4, Sec. 5
+ *
+ * Conventions common to every call
+ *   - Buffer pointers marked "device" are device (HBM) pointers owned by the
+ *     caller; the library never frees or retains them beyond the call, except
+ *     the point buffer held by a batch plan (see pcr_batch_create).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls only
+ *     enqueue work on `stream` and return; they never synchronise.  Results are
+ *     valid once the stream has reached the call.
+ *   - Return value: PCR_OK (0) or a negative PCR_E* code.  pcr_last_error()
+ *     then returns a message for the calling thread.  Argument errors are
+ *     detected on the host before anything is enqueued.  A fault inside a
+ *     kernel is reported by HIP on a later call or stream synchronisation.
+ *   - Render-path calls (clear, render, resolve, reorder, batch launch)
+ *     allocate no memory.
+ *   - Images: row-major, W*H pixels, row 0 is the bottom row (NDC y = -1).
+ *
+ * Points
+ *   16-byte records {float x, y, z; uint32 rgba}, 16-byte aligned, colour red
+ *   in bits 0-7, green 8-15, blue 16-23, alpha 24-31 (Sec. 5 quotes 16 bytes
+ *   per point for every data set).
+ *
+ * Projection (Sec. 3.1; the paper leaves the pixel mapping open, this is the
+ * library's reading): clip = MVP * (x, y, z, 1) in float32, each row summed
+ * left to right with one rounding per operation and no fused multiply-add; the
+ * point is culled unless w > 0; rw = 1/w correctly rounded; fx = (cx*rw + 1) *
+ * (W/2), fy = (cy*rw + 1) * (H/2); culled unless 0 <= fx < W and 0 <= fy < H;
+ * pixel (trunc fx, trunc fy); the depth is the linear w (Sec. 3.1 closing
+ * paragraph).  Clip z is not used (no near/far clipping).
+ */
+#ifndef PCR_H
+#define PCR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pcr_point {
+    float x, y, z;
+    uint32_t rgba;
+} pcr_point;
+
+/* Status codes. */
+enum {
+    PCR_OK = 0,
+    PCR_EINVAL = -1,      /* bad argument (nothing was enqueued) */
+    PCR_EHIP = -2,        /* a HIP call failed */
+    PCR_ENOMEM = -3,      /* scratch too small or allocation failed */
+    PCR_EUNSUPPORTED = -4 /* valid request the build does not support */
+};
+
+/* Variants (low byte of `variant`).
+ * PCR_BASIC  closest point per pixel by 64-bit atomicMin (Sec. 3.1).
+ * PCR_DEDUP  the same image; same-pixel updates are merged inside each
+ *            wavefront and workgroup before the global atomic, and the global
+ *            atomic is skipped when the stored key is already smaller
+ *            (Sec. 3.2-3.4).
+ * PCR_HQ     blended colour of the points within 1% of the closest depth of
+ *            each pixel: depth pass, colour pass, integer resolve (Sec. 3.5). */
+enum { PCR_BASIC = 0, PCR_DEDUP = 1, PCR_HQ = 2 };
+
+/* Flag bits OR-ed into `variant`.  For PCR_BASIC and PCR_DEDUP they select the
+ * update path only; every combination yields bit-identical framebuffers.  With
+ * PCR_DEDUP and none of EARLYZ/REDUCE/LDS, the tuned default set is used.
+ *   PCR_F_EARLYZ  read the stored value first, skip the atomic when it is not
+ *                 larger (Sec. 3.2; safe because values only decrease)
+ *   PCR_F_REDUCE  merge runs of equal pixels inside a wavefront before the
+ *                 atomic (Sec. 3.3, generalised from pairs and all-equal)
+ *   PCR_F_LDS     merge all equal pixels of a workgroup's tile in an LDS hash
+ *                 table before the atomics (Sec. 3.4's deduplication)
+ *   PCR_F_HQ_DEPTH / PCR_F_HQ_COLOR  (PCR_HQ) run only that pass; neither bit
+ *                 = both passes in order.  Running the depth pass over several
+ *                 point buffers and then the colour pass over the same buffers
+ *                 renders their union. */
+enum {
+    PCR_F_EARLYZ = 1 << 8,
+    PCR_F_REDUCE = 1 << 9,
+    PCR_F_LDS = 1 << 10,
+    PCR_F_HQ_DEPTH = 1 << 12,
+    PCR_F_HQ_COLOR = 1 << 13
+};
+
+/* Vertex orders (Sec. 4, Sec. 5). */
+enum {
+    PCR_ORDER_MORTON = 0,         /* stable sort by 63-bit Morton code */
+    PCR_ORDER_MORTON_SHUFFLE = 1, /* Morton, then batches moved to random places */
+    PCR_ORDER_SHUFFLE = 2         /* sort by one random key per point */
+};
+
+/* Launch shape for the render kernels.  Zero fields take the defaults.
+ *   ppt   points per thread (1, 2, 4, 8 or 16)
+ *   wg    workgroup size (64, 128, 256, 512 or 1024)
+ *   grid  workgroups per launch (0 = enough for one tile per workgroup)
+ *   group views per point pass in a batch (0 = all that fit the cache budget) */
+typedef struct pcr_tune {
+    uint32_t ppt;
+    uint32_t wg;
+    uint32_t grid;
+    uint32_t group;
+} pcr_tune;
+
+/* Framebuffer layout (device memory, size pcr_fb_bytes):
+ *   PCR_BASIC / PCR_DEDUP: uint64 key[W*H]; key = (depth bits << 32) | rgba,
+ *     cleared to all ones; the smallest key of a pixel is its closest point
+ *     (ties in depth go to the smaller colour word).
+ *   PCR_HQ: uint32 depth[W*H] (float bits, cleared to 0xFFFFFFFF), then at the
+ *     next 256-byte boundary uint64 sum[2*W*H] with sum[2p] = (R sum << 32) |
+ *     G sum and sum[2p+1] = (B sum << 32) | count, each word modulo 2^64
+ *     (Sec. 3.5 packs the four 32-bit channels into two 64-bit integers).
+ * Returns 0 for invalid sizes or variants. */
+size_t pcr_fb_bytes(uint32_t w, uint32_t h, int variant);
+
+/* Clears a framebuffer for a new frame.  fb: device, pcr_fb_bytes(w, h,
+ * variant) bytes, 16-byte aligned.  w, h in [1, 2^24), w*h < 2^32. */
+int pcr_fb_clear(void *fb, uint32_t w, uint32_t h, int variant, void *stream);
+
+/* Renders n points into fb (Sec. 3.1-3.5).
+ *   pts  device, n records, 16-byte aligned (ignored when n == 0)
+ *   mvp  host, 16 floats, row-major (mvp[4*row + col]); copied by value, the
+ *        array may be reused as soon as the call returns
+ *   fb   device framebuffer of the variant, cleared by pcr_fb_clear
+ * Basic and dedup accumulate: several calls on one framebuffer render the union
+ * of their points.  PCR_HQ runs its depth pass and then its colour pass over
+ * `pts` (or only the pass named by a PCR_F_HQ_* bit).  n == 0 is a no-op.
+ * Errors: PCR_EINVAL for null or misaligned pointers, bad sizes, unknown
+ * variant or flag bits. */
+int pcr_render(const pcr_point *pts, uint64_t n, const float mvp[16], uint32_t w, uint32_t h,
+               int variant, void *fb, void *stream);
+
+/* pcr_render with an explicit launch shape (tune may be NULL). */
+int pcr_render_ex(const pcr_point *pts, uint64_t n, const float mvp[16], uint32_t w, uint32_t h,
+                  int variant, void *fb, const pcr_tune *tune, void *stream);
+
+/* Resolve pass (Sec. 3.1 second listing, Sec. 3.5 resolve listing).
+ *   rgba_out  device, uint32[W*H].
+ * Basic/dedup: the colour word of the stored key, 0 where nothing landed.
+ * HQ: per channel floor(sum / count) (integer division), alpha 255; 0 where
+ * the count is 0. */
+int pcr_resolve(const void *fb, uint32_t w, uint32_t h, int variant, uint32_t *rgba_out,
+                void *stream);
+
+/* Device scratch needed by pcr_reorder for n points (0 if n is too large). */
+size_t pcr_reorder_scratch_bytes(uint64_t n, int order, uint32_t batch);
+
+/* Reorders a point buffer (Sec. 4: Morton order and shuffled Morton order;
+ * Sec. 5: the shuffled order and the 21-level Morton code).
+ *   in, out    device, n records each, must not overlap
+ *   perm_out   device uint32[n] or NULL: perm_out[j] = input index of out[j]
+ *   order      PCR_ORDER_*
+ *   batch      batch size of PCR_ORDER_MORTON_SHUFFLE (the paper uses 128)
+ *   seed       seed of the shuffle keys: batch b (or point i) gets the b-th
+ *              (i-th) output of SplitMix64 seeded with `seed`, and batches are
+ *              emitted in ascending (key, index) order
+ *   scratch    device, scratch_bytes >= pcr_reorder_scratch_bytes(n, order, batch)
+ * Morton codes interleave 21-bit cell indices of the cubic bounding box
+ * (x in bit 3i, y in 3i+1, z in 3i+2); cell = min(trunc(((v - lo) / size) *
+ * 2^21), 2^21 - 1) in float32.  Equal codes keep their input order.  n must be
+ * below 2^32; coordinates must be finite. */
+int pcr_reorder(const pcr_point *in, pcr_point *out, uint32_t *perm_out, uint64_t n, int order,
+                uint32_t batch, uint64_t seed, void *scratch, size_t scratch_bytes, void *stream);
+
+/* One view of a batch: camera, image size, variant and its buffers. */
+typedef struct pcr_view {
+    float mvp[16];      /* row-major */
+    uint32_t w, h;
+    int32_t variant;    /* PCR_BASIC, PCR_DEDUP or PCR_HQ (flag bits ignored); -1 = unused slot */
+    uint32_t reserved;
+    void *fb;           /* device framebuffer of the variant (cleared by the batch) */
+    uint32_t *rgba_out; /* device uint32[w*h], resolved image */
+} pcr_view;
+
+/* A batch plan renders up to `capacity` views of one resident point buffer per
+ * launch: the framebuffers are cleared, every view's points are rendered in
+ * persistent kernels that load each point once per group of views, and every
+ * view is resolved.  The launch is a single hipGraph replay.  Each view's
+ * image is bit-identical to pcr_fb_clear + pcr_render + pcr_resolve of that
+ * view alone.  The plan allocates its device view table and graph at
+ * creation; pcr_batch_launch allocates nothing.  A plan is not thread-safe;
+ * launches of one plan on different streams must not overlap. */
+typedef struct pcr_batch pcr_batch;
+
+int pcr_batch_create(pcr_batch **plan, const pcr_point *pts, uint64_t n, uint32_t capacity,
+                     const pcr_tune *tune, void *stream);
+
+/* Enqueues one batch: views[0..nviews) (host array, copied before return),
+ * nviews <= capacity. */
+int pcr_batch_launch(pcr_batch *plan, const pcr_view *views, uint32_t nviews, void *stream);
+
+int pcr_batch_destroy(pcr_batch *plan);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *pcr_last_error(void);
+
+/* Library version string. */
+const char *pcr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCR_H */

@@ -1,0 +1,109 @@
+// pcr_api.hip -- host-side plumbing of the C ABI: argument checks, launch
+// shapes, error messages.
+#include <mutex>
+#include <string>
+
+#include "pcr_internal.h"
+
+namespace pcr {
+
+namespace {
+thread_local std::string g_error;
+}
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+int check_image(uint32_t w, uint32_t h) {
+    if (w == 0 || h == 0) return fail(PCR_EINVAL, "image size %ux%u is empty", w, h);
+    if (w >= (1u << 24) || h >= (1u << 24))
+        return fail(PCR_EINVAL, "image size %ux%u: each side must be below 2^24", w, h);
+    if ((uint64_t)w * h >= (1ull << 32))
+        return fail(PCR_EINVAL, "image size %ux%u: at most 2^32 - 1 pixels", w, h);
+    return PCR_OK;
+}
+
+int check_variant(int variant) {
+    if (variant < 0) return fail(PCR_EINVAL, "unknown variant %d", variant);
+    int fam = variant & 0xFF;
+    uint32_t flags = (uint32_t)variant & ~0xFFu;
+    if (fam != PCR_BASIC && fam != PCR_DEDUP && fam != PCR_HQ)
+        return fail(PCR_EINVAL, "unknown variant %d", fam);
+    uint32_t allowed = fam == PCR_HQ ? (PCR_F_EARLYZ | PCR_F_LDS | kHqPassMask) : kFlagMask;
+    if (flags & ~allowed) return fail(PCR_EINVAL, "flag bits 0x%x do not apply to variant %d", flags & ~allowed, fam);
+    return PCR_OK;
+}
+
+size_t hq_depth_bytes(uint32_t w, uint32_t h) {
+    size_t b = 4ull * w * h;
+    return (b + 255) & ~(size_t)255;
+}
+
+static bool pow2_in(uint32_t v, uint32_t lo, uint32_t hi) {
+    return v >= lo && v <= hi && (v & (v - 1)) == 0;
+}
+
+int resolve_shape(const pcr_tune *tune, int family, Shape &s) {
+    // Defaults: a tile of 1024 points per 256-thread workgroup for the plain
+    // kernels, 2048 for the LDS-deduplicating ones.
+    s.wg = 256;
+    s.ppt = family == PCR_DEDUP ? 8 : 4;
+    s.grid = 0;
+    if (tune) {
+        if (tune->wg) s.wg = tune->wg;
+        if (tune->ppt) s.ppt = tune->ppt;
+        s.grid = tune->grid;
+    }
+    if (!pow2_in(s.wg, 64, 1024)) return fail(PCR_EINVAL, "workgroup size %u is not a power of two in [64, 1024]", s.wg);
+    if (!pow2_in(s.ppt, 1, 16)) return fail(PCR_EINVAL, "points per thread %u is not 1, 2, 4, 8 or 16", s.ppt);
+    return PCR_OK;
+}
+
+int device_cus() {
+    static std::mutex mu;
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    std::lock_guard<std::mutex> g(mu);
+    if (cache[dev] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+        cache[dev] = v;
+    }
+    return cache[dev];
+}
+
+size_t max_lds() {
+    static std::mutex mu;
+    static size_t cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 64 * 1024;
+    std::lock_guard<std::mutex> g(mu);
+    if (cache[dev] == 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            v = 64 * 1024;
+        cache[dev] = (size_t)v;
+    }
+    return cache[dev];
+}
+
+int allow_lds(const void *kernel, size_t bytes) {
+    if (bytes <= 64 * 1024) return PCR_OK;
+    hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return fail(PCR_EHIP, "hipFuncSetAttribute(%zu bytes of LDS): %s", bytes, hipGetErrorString(e));
+    return PCR_OK;
+}
+
+}  // namespace pcr
+
+extern "C" const char *pcr_last_error(void) { return pcr::g_error.c_str(); }
+
+extern "C" const char *pcr_version(void) { return "pcr 0.1 (gfx950)"; }

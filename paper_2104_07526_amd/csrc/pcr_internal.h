@@ -1,0 +1,139 @@
+// pcr_internal.h -- device helpers and host plumbing shared by the libpcr
+// translation units (GPU library only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+
+#include "pcr.h"
+
+// Every float operation of the projection is one IEEE binary32 operation
+// (no contraction into fused multiply-add), matching the fixed operation
+// order documented in pcr.h.
+#pragma clang fp contract(off)
+
+namespace pcr {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned long long u64;
+
+constexpr u64 kEmptyKey = ~0ull;
+constexpr uint32_t kEmptyPid = 0xFFFFFFFFu;
+constexpr uint32_t kFlagMask = PCR_F_EARLYZ | PCR_F_REDUCE | PCR_F_LDS;
+constexpr uint32_t kHqPassMask = PCR_F_HQ_DEPTH | PCR_F_HQ_COLOR;
+
+// Camera and viewport of one view, passed by value as a kernel argument (the
+// matrix is read through scalar loads and used as SGPR operands).
+struct View {
+    float m[16];
+    uint32_t W, H;
+    float fW, fH, hw, hh;
+};
+
+inline View make_view(const float *mvp, uint32_t W, uint32_t H) {
+    View v;
+    for (int i = 0; i < 16; ++i) v.m[i] = mvp[i];
+    v.W = W;
+    v.H = H;
+    v.fW = (float)W;
+    v.fH = (float)H;
+    v.hw = 0.5f * v.fW;
+    v.hh = 0.5f * v.fH;
+    return v;
+}
+
+// Projection (Sec. 3.1): clip = M * (x, y, z, 1); cull unless w > 0; one
+// correctly rounded reciprocal; half-open viewport test in float; truncation.
+// Returns the pixel index, or kEmptyPid when the point is culled, and the
+// depth bits (the linear w) in dbits.
+__device__ __forceinline__ uint32_t project(const View &v, float x, float y, float z,
+                                            uint32_t &dbits) {
+    float cx = ((v.m[0] * x + v.m[1] * y) + v.m[2] * z) + v.m[3];
+    float cy = ((v.m[4] * x + v.m[5] * y) + v.m[6] * z) + v.m[7];
+    float cw = ((v.m[12] * x + v.m[13] * y) + v.m[14] * z) + v.m[15];
+    float rw = 1.0f / cw;
+    float fx = (cx * rw + 1.0f) * v.hw;
+    float fy = (cy * rw + 1.0f) * v.hh;
+    bool ok = (cw > 0.0f) && (fx >= 0.0f) && (fx < v.fW) && (fy >= 0.0f) && (fy < v.fH);
+    dbits = __float_as_uint(cw);
+    uint32_t px = (uint32_t)(ok ? fx : 0.0f);
+    uint32_t py = (uint32_t)(ok ? fy : 0.0f);
+    return ok ? py * v.W + px : kEmptyPid;
+}
+
+__device__ __forceinline__ u32x4 load_point(const u32x4 *p) {
+    return __builtin_nontemporal_load(p);
+}
+
+__device__ __forceinline__ u64 make_key(uint32_t dbits, uint32_t rgba) {
+    return ((u64)dbits << 32) | (u64)rgba;
+}
+
+// Relaxed (non-synchronising) read of a framebuffer word for the early depth
+// test.  A stale value is always >= the current one, so a stale read only costs
+// a superfluous atomic, never a wrong skip (Sec. 3.2).
+__device__ __forceinline__ u64 peek_u64(const u64 *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t peek_u32(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void gmin_u64(u64 *p, u64 v) {
+    __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gmin_u32(uint32_t *p, uint32_t v) {
+    __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gadd_u64(u64 *p, u64 v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Tile index of workgroup b when every workgroup takes one tile: consecutive
+// workgroups are dispatched round-robin over the 8 XCDs, so XCD x is given the
+// contiguous tile range [x*T/8, (x+1)*T/8) and each XCD's L2 sees its own part
+// of a spatially ordered cloud.
+__device__ __forceinline__ uint64_t xcd_tile(uint64_t b, uint64_t ntiles) {
+    uint64_t per = (ntiles + 7) / 8;
+    return (b % 8) * per + b / 8;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int device_cus();
+size_t max_lds();
+int allow_lds(const void *kernel, size_t bytes);
+
+#define PCR_HIP(call)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ::pcr::fail(PCR_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define PCR_LAUNCHED()                                                                 \
+    do {                                                                               \
+        hipError_t e_ = hipGetLastError();                                             \
+        if (e_ != hipSuccess)                                                          \
+            return ::pcr::fail(PCR_EHIP, "kernel launch failed: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+int check_image(uint32_t w, uint32_t h);
+int check_variant(int variant);
+size_t hq_depth_bytes(uint32_t w, uint32_t h);
+
+struct Shape {
+    uint32_t ppt, wg, grid;
+};
+int resolve_shape(const pcr_tune *tune, int family, Shape &s);
+
+// Kernels launched by more than one translation unit.
+int launch_fill(void *p, size_t bytes, uint32_t word, hipStream_t s);
+
+}  // namespace pcr

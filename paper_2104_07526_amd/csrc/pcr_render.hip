@@ -1,0 +1,604 @@
+// pcr_render.hip -- clear, render and resolve kernels of the point rasterizer
+// (Sec. 3.1-3.5) and their host launchers.
+//
+// Data layout in HBM: points are a 16-byte array streamed once per geometry
+// pass with non-temporal 16-byte loads (one point per lane, 1 KiB per wave per
+// load); framebuffers are small (7-166 MB) and stay in L2 / Infinity Cache.
+#include "pcr_internal.h"
+
+namespace pcr {
+
+// ---------------------------------------------------------------------------
+// Clear: 16-byte stores of a 32-bit pattern (no hipMemset, so the clear can be
+// captured in a graph).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_fill(u32x4 *__restrict__ p, uint64_t n16, uint32_t word,
+                                              uint32_t *__restrict__ tail, uint32_t ntail) {
+    const u32x4 v = {word, word, word, word};
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+        __builtin_nontemporal_store(v, p + i);
+    if (blockIdx.x == 0 && threadIdx.x < ntail) tail[threadIdx.x] = word;
+}
+
+int launch_fill(void *p, size_t bytes, uint32_t word, hipStream_t s) {
+    if (bytes == 0) return PCR_OK;
+    uint64_t n16 = bytes / 16;
+    uint32_t ntail = (uint32_t)((bytes % 16) / 4);
+    uint32_t *tail = (uint32_t *)((char *)p + n16 * 16);
+    uint64_t want = (n16 + 255) / 256;
+    uint32_t grid = (uint32_t)(want < 1 ? 1 : (want > 8192 ? 8192 : want));
+    hipLaunchKernelGGL(k_fill, dim3(grid), dim3(256), 0, s, (u32x4 *)p, n16, word, tail, ntail);
+    PCR_LAUNCHED();
+    return PCR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront reduction of Sec. 3.3 on a 64-lane wavefront: when every live lane
+// targets one pixel, only the lanes holding the wave's minimum write (first
+// listing); otherwise neighbouring lane pairs merge (second listing).  Keys are
+// compared whole, so a lane that loses can never hold the pixel's minimum.
+// ---------------------------------------------------------------------------
+template <typename V>
+__device__ __forceinline__ V wave_min(V x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        V y = __shfl_xor(x, o, 64);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+template <typename V>
+__device__ __forceinline__ V lane_pair(V x) {
+    // quad_perm [1,0,3,2]: exchange with lane ^ 1.
+    if constexpr (sizeof(V) == 8) {
+        uint32_t lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)x, 0xB1, 0xF, 0xF, false);
+        uint32_t hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(x >> 32), 0xB1, 0xF, 0xF, false);
+        return ((V)hi << 32) | lo;
+    } else {
+        return (V)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, false);
+    }
+}
+
+template <typename V>
+__device__ __forceinline__ bool wave_reduce(uint32_t pid, V val, bool live) {
+    uint64_t lm = __ballot(live);
+    if (lm == 0) return false;
+    uint32_t first = (uint32_t)__builtin_ctzll(lm);
+    uint32_t p0 = __shfl(pid, first, 64);
+    if (__ballot(live && pid == p0) == lm) {
+        V m = wave_min(live ? val : (V)~(V)0);
+        return live && val == m;
+    }
+    uint32_t ppid = lane_pair(pid);
+    V pval = lane_pair(val);
+    uint32_t lane = __lane_id();
+    bool same = ppid == pid;  // both live: a culled lane carries kEmptyPid
+    bool lose = same && (pval < val || (pval == val && (lane & 1)));
+    return live && !lose;
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup deduplication in LDS (Sec. 3.4 realised without partition
+// intrinsics): an open-addressing hash table keyed by pixel index, one slot
+// per distinct pixel of the tile, merged with LDS atomics, then one global
+// atomic per distinct pixel.
+// Shared memory: count[2] | val[HS] | tag[HS] | list[T].
+// ---------------------------------------------------------------------------
+struct Sum2 {
+    u64 rg, ba;
+};
+
+template <typename V>
+struct Lds {
+    uint32_t *count;
+    V *val;
+    uint32_t *tag;
+    uint32_t *list;
+    uint32_t mask, shift;
+
+    __device__ Lds(void *smem, uint32_t hbits) {
+        count = (uint32_t *)smem;
+        val = (V *)((char *)smem + 16);
+        tag = (uint32_t *)(val + (1u << hbits));
+        list = tag + (1u << hbits);
+        mask = (1u << hbits) - 1u;
+        shift = 32u - hbits;
+    }
+
+    // Slot of pixel `pid`, claimed if new (then appended to the list of the
+    // tile with parity `par`).  The table is at most half full, so the probe
+    // sequence always reaches the pixel's slot or a free one.
+    __device__ __forceinline__ uint32_t slot(uint32_t pid, uint32_t par) {
+        uint32_t h = (pid * 0x9E3779B1u) >> shift;
+        for (;;) {
+            uint32_t t = __hip_atomic_load(tag + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (t == pid) return h;
+            if (t == kEmptyPid) {
+                uint32_t old = atomicCAS(tag + h, kEmptyPid, pid);
+                if (old == kEmptyPid) {
+                    list[atomicAdd(count + par, 1u)] = h;
+                    return h;
+                }
+                if (old == pid) return h;
+            }
+            h = (h + 1u) & mask;
+        }
+    }
+};
+
+inline size_t lds_bytes(uint32_t T, uint32_t hbits, size_t vbytes) {
+    return 16 + ((size_t)vbytes + 4) * (1u << hbits) + 4ull * T;
+}
+
+inline uint32_t lds_hbits(uint32_t T) {
+    uint32_t b = 1;
+    while ((1u << b) < 2u * T) ++b;  // at most half full
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// Render kernels.  One tile = wg * PPT consecutive points; lane t loads points
+// tile*T + j*wg + t (j < PPT), all loads issued before any use.
+// ---------------------------------------------------------------------------
+struct Tiles {
+    uint64_t n, ntiles, nblocks;
+    int remap;
+    __device__ __forceinline__ bool tile(uint64_t b, uint64_t &t) const {
+        t = remap ? xcd_tile(b, ntiles) : b;
+        return t < ntiles;
+    }
+};
+
+template <int PPT>
+__device__ __forceinline__ void load_tile(const u32x4 *__restrict__ pts, uint64_t base, uint32_t wg,
+                                          uint64_t n, u32x4 (&p)[PPT]) {
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        uint64_t i = base + (uint64_t)j * wg;
+        p[j] = i < n ? load_point(pts + i) : u32x4{0u, 0u, 0u, 0u};
+    }
+}
+
+// Basic closest-point render (Sec. 3.1), optionally with the early depth test
+// (Sec. 3.2) and the wavefront reduction (Sec. 3.3).
+template <int PPT, bool EARLYZ, bool REDUCE>
+__global__ __launch_bounds__(1024) void k_basic(const u32x4 *__restrict__ pts, Tiles tl, View v,
+                                                u64 *__restrict__ fb) {
+    const uint32_t wg = blockDim.x;
+    for (uint64_t b = blockIdx.x; b < tl.nblocks; b += gridDim.x) {
+        uint64_t t;
+        if (!tl.tile(b, t)) continue;
+        uint64_t base = t * wg * PPT + threadIdx.x;
+        u32x4 p[PPT];
+        load_tile<PPT>(pts, base, wg, tl.n, p);
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            uint32_t dbits;
+            uint32_t pid = project(v, __uint_as_float(p[j].x), __uint_as_float(p[j].y),
+                                   __uint_as_float(p[j].z), dbits);
+            if (base + (uint64_t)j * wg >= tl.n) pid = kEmptyPid;
+            u64 key = make_key(dbits, p[j].w);
+            bool w = pid != kEmptyPid;
+            if (REDUCE) w = wave_reduce<u64>(pid, key, w);
+            if (EARLYZ && w) w = key < peek_u64(fb + pid);
+            if (w) gmin_u64(fb + pid, key);
+        }
+    }
+}
+
+// Closest-point render with LDS deduplication (Sec. 3.4); V = u64 keys for the
+// basic framebuffer, V = uint32 depth bits for the HQ depth pass (Sec. 3.5).
+template <typename V, int PPT, bool EARLYZ, bool REDUCE>
+__global__ __launch_bounds__(1024) void k_dedup(const u32x4 *__restrict__ pts, Tiles tl, View v,
+                                                V *__restrict__ fb, uint32_t hbits) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    Lds<V> L(smem, hbits);
+    const uint32_t wg = blockDim.x;
+    const uint32_t HS = 1u << hbits;
+    for (uint32_t s = threadIdx.x; s < HS; s += wg) {
+        L.tag[s] = kEmptyPid;
+        L.val[s] = (V)~(V)0;
+    }
+    if (threadIdx.x < 2) L.count[threadIdx.x] = 0;
+    __syncthreads();
+    uint32_t par = 0;
+    for (uint64_t b = blockIdx.x; b < tl.nblocks; b += gridDim.x) {
+        uint64_t t;
+        if (!tl.tile(b, t)) continue;
+        uint64_t base = t * wg * PPT + threadIdx.x;
+        u32x4 p[PPT];
+        load_tile<PPT>(pts, base, wg, tl.n, p);
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            uint32_t dbits;
+            uint32_t pid = project(v, __uint_as_float(p[j].x), __uint_as_float(p[j].y),
+                                   __uint_as_float(p[j].z), dbits);
+            if (base + (uint64_t)j * wg >= tl.n) pid = kEmptyPid;
+            V val;
+            if constexpr (sizeof(V) == 8)
+                val = make_key(dbits, p[j].w);
+            else
+                val = dbits;
+            bool w = pid != kEmptyPid;
+            if (REDUCE) w = wave_reduce<V>(pid, val, w);
+            if (w) {
+                uint32_t h = L.slot(pid, par);
+                __hip_atomic_fetch_min(L.val + h, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+        __syncthreads();
+        uint32_t cnt = L.count[par];
+        if (threadIdx.x == 0) L.count[par ^ 1u] = 0;
+        for (uint32_t k = threadIdx.x; k < cnt; k += wg) {
+            uint32_t h = L.list[k];
+            uint32_t pid = L.tag[h];
+            V val = L.val[h];
+            L.tag[h] = kEmptyPid;
+            L.val[h] = (V)~(V)0;
+            bool w = true;
+            if constexpr (sizeof(V) == 8) {
+                if (EARLYZ) w = val < peek_u64(fb + pid);
+                if (w) gmin_u64(fb + pid, val);
+            } else {
+                if (EARLYZ) w = val < peek_u32(fb + pid);
+                if (w) gmin_u32(fb + pid, val);
+            }
+        }
+        __syncthreads();
+        par ^= 1u;
+    }
+}
+
+// HQ depth pass without LDS (Sec. 3.5: a 32-bit atomicMin of the depth).
+template <int PPT, bool EARLYZ>
+__global__ __launch_bounds__(1024) void k_hq_depth(const u32x4 *__restrict__ pts, Tiles tl, View v,
+                                                   uint32_t *__restrict__ D) {
+    const uint32_t wg = blockDim.x;
+    for (uint64_t b = blockIdx.x; b < tl.nblocks; b += gridDim.x) {
+        uint64_t t;
+        if (!tl.tile(b, t)) continue;
+        uint64_t base = t * wg * PPT + threadIdx.x;
+        u32x4 p[PPT];
+        load_tile<PPT>(pts, base, wg, tl.n, p);
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            uint32_t dbits;
+            uint32_t pid = project(v, __uint_as_float(p[j].x), __uint_as_float(p[j].y),
+                                   __uint_as_float(p[j].z), dbits);
+            if (base + (uint64_t)j * wg >= tl.n) pid = kEmptyPid;
+            bool w = pid != kEmptyPid;
+            if (EARLYZ && w) w = dbits < peek_u32(D + pid);
+            if (w) gmin_u32(D + pid, dbits);
+        }
+    }
+}
+
+// HQ colour pass (Sec. 3.5): a point within 1% of its pixel's closest depth
+// adds (r << 32 | g) and (b << 32 | 1) to the pixel's two 64-bit sums.
+__device__ __forceinline__ bool hq_contributes(const uint32_t *__restrict__ D, uint32_t pid,
+                                               uint32_t dbits) {
+    float limit = __uint_as_float(D[pid]) * 1.01f;
+    return __uint_as_float(dbits) <= limit;
+}
+
+template <int PPT, bool LDS>
+__global__ __launch_bounds__(1024) void k_hq_color(const u32x4 *__restrict__ pts, Tiles tl, View v,
+                                                   const uint32_t *__restrict__ D,
+                                                   u64 *__restrict__ S, uint32_t hbits) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const uint32_t wg = blockDim.x;
+    Lds<Sum2> L(smem, hbits);
+    if (LDS) {
+        for (uint32_t s = threadIdx.x; s < (1u << hbits); s += wg) {
+            L.tag[s] = kEmptyPid;
+            L.val[s].rg = 0;
+            L.val[s].ba = 0;
+        }
+        if (threadIdx.x < 2) L.count[threadIdx.x] = 0;
+        __syncthreads();
+    }
+    uint32_t par = 0;
+    for (uint64_t b = blockIdx.x; b < tl.nblocks; b += gridDim.x) {
+        uint64_t t;
+        if (!tl.tile(b, t)) continue;
+        uint64_t base = t * wg * PPT + threadIdx.x;
+        u32x4 p[PPT];
+        load_tile<PPT>(pts, base, wg, tl.n, p);
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            uint32_t dbits;
+            uint32_t pid = project(v, __uint_as_float(p[j].x), __uint_as_float(p[j].y),
+                                   __uint_as_float(p[j].z), dbits);
+            if (base + (uint64_t)j * wg >= tl.n) pid = kEmptyPid;
+            if (pid == kEmptyPid || !hq_contributes(D, pid, dbits)) continue;
+            u64 r = p[j].w & 0xFFu, g = (p[j].w >> 8) & 0xFFu, bl = (p[j].w >> 16) & 0xFFu;
+            u64 rg = (r << 32) | g, ba = (bl << 32) | 1u;
+            if (!LDS) {
+                gadd_u64(S + 2 * (u64)pid, rg);
+                gadd_u64(S + 2 * (u64)pid + 1, ba);
+                continue;
+            }
+            uint32_t h = L.slot(pid, par);
+            __hip_atomic_fetch_add(&L.val[h].rg, rg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(&L.val[h].ba, ba, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        if (!LDS) continue;
+        __syncthreads();
+        uint32_t cnt = L.count[par];
+        if (threadIdx.x == 0) L.count[par ^ 1u] = 0;
+        for (uint32_t k = threadIdx.x; k < cnt; k += wg) {
+            uint32_t h = L.list[k];
+            uint32_t pid = L.tag[h];
+            Sum2 sm = L.val[h];
+            L.tag[h] = kEmptyPid;
+            L.val[h].rg = 0;
+            L.val[h].ba = 0;
+            gadd_u64(S + 2 * (u64)pid, sm.rg);
+            gadd_u64(S + 2 * (u64)pid + 1, sm.ba);
+        }
+        __syncthreads();
+        par ^= 1u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Resolve (Sec. 3.1 second listing; Sec. 3.5 resolve listing).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_resolve_basic(const u64 *__restrict__ fb,
+                                                       uint32_t *__restrict__ out, uint64_t npix) {
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npix; i += stride) {
+        u64 k = fb[i];
+        out[i] = k == kEmptyKey ? 0u : (uint32_t)k;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_resolve_hq(const u32x4 *__restrict__ S,
+                                                    uint32_t *__restrict__ out, uint64_t npix) {
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npix; i += stride) {
+        u32x4 s = S[i];  // {G sum, R sum, count, B sum}
+        uint32_t c = s.z;
+        uint32_t o = 0;
+        if (c != 0) {
+            uint32_t r = s.y / c, g = s.x / c, b = s.w / c;
+            o = (r & 0xFFu) | (g & 0xFFu) << 8 | (b & 0xFFu) << 16 | 0xFF000000u;
+        }
+        out[i] = o;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+namespace {
+
+Tiles make_tiles(uint64_t n, const Shape &sh, uint32_t &grid) {
+    Tiles tl;
+    tl.n = n;
+    uint64_t T = (uint64_t)sh.wg * sh.ppt;
+    tl.ntiles = (n + T - 1) / T;
+    if (sh.grid == 0) {
+        // One tile per workgroup, XCD-contiguous tile ranges.
+        tl.remap = 1;
+        tl.nblocks = ((tl.ntiles + 7) / 8) * 8;
+        uint64_t g = tl.nblocks;
+        grid = (uint32_t)(g > 0x7FFFFFFFull ? 0x7FFFFFFFull : g);
+    } else {
+        tl.remap = 0;
+        tl.nblocks = tl.ntiles;
+        uint64_t g = tl.ntiles < sh.grid ? tl.ntiles : sh.grid;
+        grid = (uint32_t)(g < 1 ? 1 : g);
+    }
+    return tl;
+}
+
+template <template <int> class F, typename... A>
+int by_ppt(uint32_t ppt, A &&...a) {
+    switch (ppt) {
+        case 1: return F<1>::run(a...);
+        case 2: return F<2>::run(a...);
+        case 4: return F<4>::run(a...);
+        case 8: return F<8>::run(a...);
+        case 16: return F<16>::run(a...);
+    }
+    return fail(PCR_EINVAL, "points per thread must be 1, 2, 4, 8 or 16 (got %u)", ppt);
+}
+
+struct Launch {
+    const u32x4 *pts;
+    uint64_t n;
+    View v;
+    void *fb;
+    Shape sh;
+    uint32_t flags;
+    hipStream_t s;
+};
+
+template <int P>
+struct BasicL {
+    static int run(const Launch &L) {
+        uint32_t grid;
+        Tiles tl = make_tiles(L.n, L.sh, grid);
+        bool ez = L.flags & PCR_F_EARLYZ, rd = L.flags & PCR_F_REDUCE;
+        u64 *fb = (u64 *)L.fb;
+        if (L.flags & PCR_F_LDS) {
+            uint32_t T = L.sh.wg * P, hb = lds_hbits(T);
+            size_t sm = lds_bytes(T, hb, 8);
+            if (sm > max_lds())
+                return fail(PCR_EINVAL, "tile of %u points needs %zu bytes of LDS", T, sm);
+#define PCR_DD(E, R)                                                                                    \
+    do {                                                                                                \
+        if (int rc_ = allow_lds((const void *)&k_dedup<u64, P, E, R>, sm)) return rc_;                  \
+        hipLaunchKernelGGL((k_dedup<u64, P, E, R>), dim3(grid), dim3(L.sh.wg), sm, L.s, L.pts, tl, L.v, fb, hb); \
+    } while (0)
+            if (ez && rd) PCR_DD(true, true);
+            else if (ez) PCR_DD(true, false);
+            else if (rd) PCR_DD(false, true);
+            else PCR_DD(false, false);
+#undef PCR_DD
+        } else {
+#define PCR_BB(E, R) hipLaunchKernelGGL((k_basic<P, E, R>), dim3(grid), dim3(L.sh.wg), 0, L.s, L.pts, tl, L.v, fb)
+            if (ez && rd) PCR_BB(true, true);
+            else if (ez) PCR_BB(true, false);
+            else if (rd) PCR_BB(false, true);
+            else PCR_BB(false, false);
+#undef PCR_BB
+        }
+        PCR_LAUNCHED();
+        return PCR_OK;
+    }
+};
+
+template <int P>
+struct DepthL {
+    static int run(const Launch &L) {
+        uint32_t grid;
+        Tiles tl = make_tiles(L.n, L.sh, grid);
+        bool ez = L.flags & PCR_F_EARLYZ;
+        uint32_t *D = (uint32_t *)L.fb;
+        if (L.flags & PCR_F_LDS) {
+            uint32_t T = L.sh.wg * P, hb = lds_hbits(T);
+            size_t sm = lds_bytes(T, hb, 4);
+            if (sm > max_lds())
+                return fail(PCR_EINVAL, "tile of %u points needs %zu bytes of LDS", T, sm);
+            int rc = allow_lds(ez ? (const void *)&k_dedup<uint32_t, P, true, false>
+                                  : (const void *)&k_dedup<uint32_t, P, false, false>, sm);
+            if (rc) return rc;
+            if (ez)
+                hipLaunchKernelGGL((k_dedup<uint32_t, P, true, false>), dim3(grid), dim3(L.sh.wg), sm,
+                                   L.s, L.pts, tl, L.v, D, hb);
+            else
+                hipLaunchKernelGGL((k_dedup<uint32_t, P, false, false>), dim3(grid), dim3(L.sh.wg), sm,
+                                   L.s, L.pts, tl, L.v, D, hb);
+        } else if (ez) {
+            hipLaunchKernelGGL((k_hq_depth<P, true>), dim3(grid), dim3(L.sh.wg), 0, L.s, L.pts, tl, L.v, D);
+        } else {
+            hipLaunchKernelGGL((k_hq_depth<P, false>), dim3(grid), dim3(L.sh.wg), 0, L.s, L.pts, tl, L.v, D);
+        }
+        PCR_LAUNCHED();
+        return PCR_OK;
+    }
+};
+
+template <int P>
+struct ColorL {
+    static int run(const Launch &L, uint32_t w, uint32_t h) {
+        uint32_t grid;
+        Tiles tl = make_tiles(L.n, L.sh, grid);
+        const uint32_t *D = (const uint32_t *)L.fb;
+        u64 *S = (u64 *)((char *)L.fb + hq_depth_bytes(w, h));
+        if (L.flags & PCR_F_LDS) {
+            uint32_t T = L.sh.wg * P, hb = lds_hbits(T);
+            size_t sm = lds_bytes(T, hb, 16);
+            if (sm > max_lds())
+                return fail(PCR_EINVAL, "tile of %u points needs %zu bytes of LDS", T, sm);
+            if (int rc = allow_lds((const void *)&k_hq_color<P, true>, sm)) return rc;
+            hipLaunchKernelGGL((k_hq_color<P, true>), dim3(grid), dim3(L.sh.wg), sm, L.s, L.pts, tl, L.v, D,
+                               S, hb);
+        } else {
+            hipLaunchKernelGGL((k_hq_color<P, false>), dim3(grid), dim3(L.sh.wg), 0, L.s, L.pts, tl, L.v, D,
+                               S, 1u);
+        }
+        PCR_LAUNCHED();
+        return PCR_OK;
+    }
+};
+
+}  // namespace
+
+int render_basic(const Launch &L) { return by_ppt<BasicL>(L.sh.ppt, L); }
+int render_hq_depth(const Launch &L) { return by_ppt<DepthL>(L.sh.ppt, L); }
+int render_hq_color(const Launch &L, uint32_t w, uint32_t h) { return by_ppt<ColorL>(L.sh.ppt, L, w, h); }
+
+}  // namespace pcr
+
+// ---------------------------------------------------------------------------
+// C ABI: framebuffers, render, resolve
+// ---------------------------------------------------------------------------
+using namespace pcr;
+
+extern "C" size_t pcr_fb_bytes(uint32_t w, uint32_t h, int variant) {
+    if (check_image(w, h) != PCR_OK || check_variant(variant) != PCR_OK) return 0;
+    uint64_t px = (uint64_t)w * h;
+    if ((variant & 0xFF) == PCR_HQ) return hq_depth_bytes(w, h) + 16 * px;
+    return 8 * px;
+}
+
+extern "C" int pcr_fb_clear(void *fb, uint32_t w, uint32_t h, int variant, void *stream) {
+    int rc = check_image(w, h);
+    if (rc == PCR_OK) rc = check_variant(variant);
+    if (rc != PCR_OK) return rc;
+    if (!fb || ((uintptr_t)fb & 15)) return fail(PCR_EINVAL, "framebuffer must be a 16-byte aligned device pointer");
+    hipStream_t s = (hipStream_t)stream;
+    uint64_t px = (uint64_t)w * h;
+    if ((variant & 0xFF) == PCR_HQ) {
+        size_t db = hq_depth_bytes(w, h);
+        rc = launch_fill(fb, db, 0xFFFFFFFFu, s);
+        if (rc == PCR_OK) rc = launch_fill((char *)fb + db, 16 * px, 0u, s);
+        return rc;
+    }
+    return launch_fill(fb, 8 * px, 0xFFFFFFFFu, s);
+}
+
+extern "C" int pcr_render_ex(const pcr_point *pts, uint64_t n, const float mvp[16], uint32_t w,
+                             uint32_t h, int variant, void *fb, const pcr_tune *tune, void *stream) {
+    int rc = check_image(w, h);
+    if (rc == PCR_OK) rc = check_variant(variant);
+    if (rc != PCR_OK) return rc;
+    if (!mvp) return fail(PCR_EINVAL, "mvp is NULL");
+    if (!fb || ((uintptr_t)fb & 15)) return fail(PCR_EINVAL, "framebuffer must be a 16-byte aligned device pointer");
+    if (n > 0 && (!pts || ((uintptr_t)pts & 15)))
+        return fail(PCR_EINVAL, "points must be a 16-byte aligned device pointer");
+    int fam = variant & 0xFF;
+    uint32_t flags = (uint32_t)variant & ~0xFFu;
+    Shape sh;
+    rc = resolve_shape(tune, fam, sh);
+    if (rc != PCR_OK) return rc;
+    if (n == 0) return PCR_OK;
+    Launch L{(const u32x4 *)pts, n, make_view(mvp, w, h), fb, sh, flags, (hipStream_t)stream};
+    if (fam == PCR_BASIC) return render_basic(L);
+    if (fam == PCR_DEDUP) {
+        if ((flags & kFlagMask) == 0) L.flags |= PCR_F_EARLYZ | PCR_F_LDS;
+        return render_basic(L);
+    }
+    // PCR_HQ
+    uint32_t pass = flags & kHqPassMask;
+    if (pass == 0) pass = kHqPassMask;
+    if (pass & PCR_F_HQ_DEPTH) {
+        Launch d = L;
+        if ((flags & kFlagMask) == 0) d.flags |= PCR_F_EARLYZ;
+        rc = render_hq_depth(d);
+        if (rc != PCR_OK) return rc;
+    }
+    if (pass & PCR_F_HQ_COLOR) rc = render_hq_color(L, w, h);
+    return rc;
+}
+
+extern "C" int pcr_render(const pcr_point *pts, uint64_t n, const float mvp[16], uint32_t w, uint32_t h,
+                          int variant, void *fb, void *stream) {
+    return pcr_render_ex(pts, n, mvp, w, h, variant, fb, nullptr, stream);
+}
+
+extern "C" int pcr_resolve(const void *fb, uint32_t w, uint32_t h, int variant, uint32_t *rgba_out,
+                           void *stream) {
+    int rc = check_image(w, h);
+    if (rc == PCR_OK) rc = check_variant(variant);
+    if (rc != PCR_OK) return rc;
+    if (!fb || ((uintptr_t)fb & 15)) return fail(PCR_EINVAL, "framebuffer must be a 16-byte aligned device pointer");
+    if (!rgba_out || ((uintptr_t)rgba_out & 3)) return fail(PCR_EINVAL, "rgba_out must be a 4-byte aligned device pointer");
+    uint64_t px = (uint64_t)w * h;
+    uint64_t want = (px + 255) / 256;
+    uint32_t grid = (uint32_t)(want > 16384 ? 16384 : want);
+    hipStream_t s = (hipStream_t)stream;
+    if ((variant & 0xFF) == PCR_HQ) {
+        const u32x4 *S = (const u32x4 *)((const char *)fb + hq_depth_bytes(w, h));
+        hipLaunchKernelGGL(k_resolve_hq, dim3(grid), dim3(256), 0, s, S, rgba_out, px);
+    } else {
+        hipLaunchKernelGGL(k_resolve_basic, dim3(grid), dim3(256), 0, s, (const u64 *)fb, rgba_out, px);
+    }
+    PCR_LAUNCHED();
+    return PCR_OK;
+}

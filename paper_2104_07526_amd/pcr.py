@@ -1,0 +1,221 @@
+"""ctypes binding of libpcr (include/pcr.h).  Argument marshalling only: every
+step of rendering and reordering runs in the library's HIP kernels.
+
+Buffers are torch tensors on the GPU (any dtype; only their bytes and device
+pointers are used).  Work is enqueued on the current torch stream unless a
+``stream`` (torch.cuda.Stream or raw handle) is given.  Nothing here
+synchronises.
+
+The library must be built (``python -m paper_2104_07526_amd.build``); loading
+fails loudly otherwise, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpcr.so")
+
+BASIC, DEDUP, HQ = 0, 1, 2
+F_EARLYZ = 1 << 8
+F_REDUCE = 1 << 9
+F_LDS = 1 << 10
+F_HQ_DEPTH = 1 << 12
+F_HQ_COLOR = 1 << 13
+ORDER_MORTON, ORDER_MORTON_SHUFFLE, ORDER_SHUFFLE = 0, 1, 2
+
+OK, EINVAL, EHIP, ENOMEM, EUNSUPPORTED = 0, -1, -2, -3, -4
+
+_lock = threading.Lock()
+_lib = None
+
+
+class PcrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pcr error {code}: {msg}")
+        self.code = code
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("ppt", ctypes.c_uint32), ("wg", ctypes.c_uint32), ("grid", ctypes.c_uint32),
+                ("group", ctypes.c_uint32)]
+
+
+class View(ctypes.Structure):
+    _fields_ = [("mvp", ctypes.c_float * 16), ("w", ctypes.c_uint32), ("h", ctypes.c_uint32),
+                ("variant", ctypes.c_int32), ("reserved", ctypes.c_uint32),
+                ("fb", ctypes.c_void_p), ("rgba_out", ctypes.c_void_p)]
+
+
+def _declare(lib):
+    P, U32, U64, I32, SZ = (ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int,
+                            ctypes.c_size_t)
+    sig = {
+        "pcr_fb_bytes": (SZ, [U32, U32, I32]),
+        "pcr_fb_clear": (I32, [P, U32, U32, I32, P]),
+        "pcr_render": (I32, [P, U64, P, U32, U32, I32, P, P]),
+        "pcr_render_ex": (I32, [P, U64, P, U32, U32, I32, P, P, P]),
+        "pcr_resolve": (I32, [P, U32, U32, I32, P, P]),
+        "pcr_reorder_scratch_bytes": (SZ, [U64, I32, U32]),
+        "pcr_reorder": (I32, [P, P, P, U64, I32, U32, U64, P, SZ, P]),
+        "pcr_batch_create": (I32, [P, P, U64, U32, P, P]),
+        "pcr_batch_launch": (I32, [P, P, U32, P]),
+        "pcr_batch_destroy": (I32, [P]),
+        "pcr_last_error": (ctypes.c_char_p, []),
+        "pcr_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+def lib():
+    """The loaded library (raises if it is not built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2104_07526_amd.build")
+            _lib = _declare(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise PcrError(rc, lib().pcr_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else 0
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return t.data_ptr() if hasattr(t, "data_ptr") else int(t)
+
+
+def _npoints(points):
+    nb = points.numel() * points.element_size()
+    if nb % 16:
+        raise ValueError("points must be 16-byte records")
+    return nb // 16
+
+
+def _mvp(m):
+    a = np.ascontiguousarray(np.asarray(m, dtype=np.float32).reshape(16))
+    return (ctypes.c_float * 16)(*a.tolist())
+
+
+def _tune(t):
+    if t is None:
+        return None
+    if isinstance(t, Tune):
+        return ctypes.byref(t)
+    return ctypes.byref(Tune(int(t.get("ppt", 0)), int(t.get("wg", 0)), int(t.get("grid", 0)),
+                             int(t.get("group", 0))))
+
+
+# ---------------------------------------------------------------------------
+
+def version() -> str:
+    return lib().pcr_version().decode()
+
+
+def fb_bytes(w, h, variant) -> int:
+    return int(lib().pcr_fb_bytes(w, h, variant))
+
+
+def alloc_fb(w, h, variant, device="cuda"):
+    import torch
+    nb = fb_bytes(w, h, variant)
+    if nb == 0:
+        raise PcrError(EINVAL, lib().pcr_last_error().decode())
+    return torch.empty((nb + 7) // 8, dtype=torch.int64, device=device)
+
+
+def fb_clear(fb, w, h, variant, stream=None):
+    _check(lib().pcr_fb_clear(_ptr(fb), w, h, variant, _stream(stream)))
+
+
+def render(points, mvp, w, h, variant, fb, tune=None, stream=None, n=None):
+    """Renders the 16-byte records of ``points`` (or the first ``n``)."""
+    n = _npoints(points) if n is None else n
+    _check(lib().pcr_render_ex(_ptr(points), n, _mvp(mvp), w, h, variant, _ptr(fb), _tune(tune),
+                               _stream(stream)))
+
+
+def resolve(fb, w, h, variant, out=None, stream=None):
+    import torch
+    if out is None:
+        out = torch.empty(w * h, dtype=torch.int32, device=fb.device)
+    _check(lib().pcr_resolve(_ptr(fb), w, h, variant, _ptr(out), _stream(stream)))
+    return out
+
+
+def reorder_scratch_bytes(n, order, batch=128) -> int:
+    return int(lib().pcr_reorder_scratch_bytes(n, order, batch))
+
+
+def reorder(points, order, batch=128, seed=0, out=None, perm=None, want_perm=True, scratch=None,
+            stream=None):
+    """Returns (reordered points, permutation or None)."""
+    import torch
+    n = _npoints(points)
+    if out is None:
+        out = torch.empty_like(points)
+    if want_perm and perm is None:
+        perm = torch.empty(n, dtype=torch.int32, device=points.device)
+    need = reorder_scratch_bytes(n, order, batch)
+    if scratch is None:
+        scratch = torch.empty(max(need, 1), dtype=torch.uint8, device=points.device)
+    nbytes = scratch.numel() * scratch.element_size()
+    _check(lib().pcr_reorder(_ptr(points), _ptr(out), _ptr(perm) if want_perm else None, n, order,
+                             batch, seed, _ptr(scratch), nbytes, _stream(stream)))
+    return out, (perm if want_perm else None)
+
+
+def make_view(mvp, w, h, variant, fb, rgba_out) -> View:
+    v = View()
+    v.mvp[:] = [float(x) for x in np.asarray(mvp, np.float32).reshape(16)]
+    v.w, v.h, v.variant = w, h, variant
+    v.fb = _ptr(fb)
+    v.rgba_out = _ptr(rgba_out)
+    return v
+
+
+class BatchPlan:
+    """Renders up to ``capacity`` views of one resident cloud per launch, as a
+    single hipGraph replay (pcr_batch_* in include/pcr.h)."""
+
+    def __init__(self, points, capacity, tune=None, stream=None):
+        self._points = points          # the plan keeps the device pointer
+        self.capacity = capacity
+        h = ctypes.c_void_p()
+        _check(lib().pcr_batch_create(ctypes.byref(h), _ptr(points), _npoints(points), capacity,
+                                      _tune(tune), _stream(stream)))
+        self._h = h
+
+    def launch(self, views, stream=None):
+        arr = (View * max(1, len(views)))(*views)
+        _check(lib().pcr_batch_launch(self._h, arr, len(views), _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(lib().pcr_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
