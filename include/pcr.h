@@ -74,15 +74,20 @@ enum {
  *            each pixel: depth pass, colour pass, integer resolve (Sec. 3.5). */
 enum { PCR_BASIC = 0, PCR_DEDUP = 1, PCR_HQ = 2 };
 
-/* Flag bits OR-ed into `variant`.  For PCR_BASIC and PCR_DEDUP they select the
- * update path only; every combination yields bit-identical framebuffers.  With
- * PCR_DEDUP and none of EARLYZ/REDUCE/LDS, the tuned default set is used.
+/* Flag bits OR-ed into `variant`.  They select the update path only: every
+ * combination yields bit-identical framebuffers.  With none of
+ * EARLYZ/REDUCE/LDS/PLAIN the variant's default path is used: PCR_BASIC = one
+ * global atomic per point; PCR_DEDUP and PCR_HQ = the tuned merging path.
  *   PCR_F_EARLYZ  read the stored value first, skip the atomic when it is not
  *                 larger (Sec. 3.2; safe because values only decrease)
- *   PCR_F_REDUCE  merge runs of equal pixels inside a wavefront before the
- *                 atomic (Sec. 3.3, generalised from pairs and all-equal)
+ *   PCR_F_REDUCE  merge same-pixel updates inside a wavefront before the
+ *                 atomic: the lanes sharing a leader lane's pixel (the
+ *                 all-lanes-equal case of Sec. 3.3, for up to two leaders),
+ *                 then neighbouring lane pairs (Sec. 3.3)
  *   PCR_F_LDS     merge all equal pixels of a workgroup's tile in an LDS hash
  *                 table before the atomics (Sec. 3.4's deduplication)
+ *   PCR_F_PLAIN   none of the above (for PCR_HQ: one global atomic per sum
+ *                 word, the paper's plain two-atomic colour pass)
  *   PCR_F_HQ_DEPTH / PCR_F_HQ_COLOR  (PCR_HQ) run only that pass; neither bit
  *                 = both passes in order.  Running the depth pass over several
  *                 point buffers and then the colour pass over the same buffers
@@ -91,6 +96,7 @@ enum {
     PCR_F_EARLYZ = 1 << 8,
     PCR_F_REDUCE = 1 << 9,
     PCR_F_LDS = 1 << 10,
+    PCR_F_PLAIN = 1 << 11,
     PCR_F_HQ_DEPTH = 1 << 12,
     PCR_F_HQ_COLOR = 1 << 13
 };
@@ -103,15 +109,18 @@ enum {
 };
 
 /* Launch shape for the render kernels.  Zero fields take the defaults.
- *   ppt   points per thread (1, 2, 4, 8 or 16)
- *   wg    workgroup size (64, 128, 256, 512 or 1024)
- *   grid  workgroups per launch (0 = enough for one tile per workgroup)
- *   group views per point pass in a batch (0 = all that fit the cache budget) */
+ *   ppt    points per thread (1, 2, 4, 8 or 16)
+ *   wg     workgroup size (64, 128, 256, 512 or 1024)
+ *   grid   workgroups per launch (0 = one tile of wg*ppt points per workgroup)
+ *   group  views per point pass in a batch (0 = all that fit the cache budget)
+ *   slots  LDS hash-table slots per workgroup of the deduplicating kernels,
+ *          rounded up to a power of two in [256, 32768] (0 = half a tile) */
 typedef struct pcr_tune {
     uint32_t ppt;
     uint32_t wg;
     uint32_t grid;
     uint32_t group;
+    uint32_t slots;
 } pcr_tune;
 
 /* Framebuffer layout (device memory, size pcr_fb_bytes):

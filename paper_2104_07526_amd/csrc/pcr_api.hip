@@ -36,7 +36,9 @@ int check_variant(int variant) {
     uint32_t flags = (uint32_t)variant & ~0xFFu;
     if (fam != PCR_BASIC && fam != PCR_DEDUP && fam != PCR_HQ)
         return fail(PCR_EINVAL, "unknown variant %d", fam);
-    uint32_t allowed = fam == PCR_HQ ? (PCR_F_EARLYZ | PCR_F_LDS | kHqPassMask) : kFlagMask;
+    uint32_t allowed = fam == PCR_HQ ? (PCR_F_EARLYZ | PCR_F_LDS | PCR_F_PLAIN | kHqPassMask) : kFlagMask;
+    if ((flags & PCR_F_PLAIN) && (flags & (PCR_F_EARLYZ | PCR_F_REDUCE | PCR_F_LDS)))
+        return fail(PCR_EINVAL, "PCR_F_PLAIN excludes the other path flags");
     if (flags & ~allowed) return fail(PCR_EINVAL, "flag bits 0x%x do not apply to variant %d", flags & ~allowed, fam);
     return PCR_OK;
 }
@@ -51,16 +53,22 @@ static bool pow2_in(uint32_t v, uint32_t lo, uint32_t hi) {
 }
 
 int resolve_shape(const pcr_tune *tune, int family, Shape &s) {
-    // Defaults: a tile of 1024 points per 256-thread workgroup for the plain
-    // kernels, 2048 for the LDS-deduplicating ones.
+    // Defaults (measured on MI355X): a tile of 1024 points per 256-thread
+    // workgroup for the plain kernels, 2048 points and 1024 LDS slots for the
+    // deduplicating ones.
     s.wg = 256;
     s.ppt = family == PCR_DEDUP ? 8 : 4;
     s.grid = 0;
+    s.group = 0;
+    s.slots = 0;
     if (tune) {
         if (tune->wg) s.wg = tune->wg;
         if (tune->ppt) s.ppt = tune->ppt;
         s.grid = tune->grid;
+        s.group = tune->group;
+        s.slots = tune->slots;
     }
+    if (s.slots > 32768) return fail(PCR_EINVAL, "slots %u above 32768", s.slots);
     if (!pow2_in(s.wg, 64, 1024)) return fail(PCR_EINVAL, "workgroup size %u is not a power of two in [64, 1024]", s.wg);
     if (!pow2_in(s.ppt, 1, 16)) return fail(PCR_EINVAL, "points per thread %u is not 1, 2, 4, 8 or 16", s.ppt);
     return PCR_OK;

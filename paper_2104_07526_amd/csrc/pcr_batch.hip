@@ -1,0 +1,516 @@
+// pcr_batch.hip -- batched multi-view rendering: many cameras and framebuffers
+// of one resident cloud per launch.
+//
+// A launch is one hipGraph replay of four kernels:
+//   clear   all views' buffers
+//   pass A  closest-point views (basic / dedup) and the depth pass of HQ views
+//   pass B  the colour pass of HQ views (needs every HQ depth complete)
+//   resolve all views
+// Passes A and B are persistent: workgroups take (group, tile) items from a
+// queue in group-major order, load the tile's points once and render them into
+// every view of the group, deduplicating same-pixel updates in LDS per view.
+// Views are grouped so that a group's framebuffers fit the cache budget, which
+// keeps the atomics of a pass inside a small, cache-resident working set while
+// the point stream is read once per group.  Every update is an integer min or
+// sum, so each view is bit-identical to rendering it alone.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "pcr_internal.h"
+
+namespace pcr {
+namespace {
+
+constexpr uint32_t kBatchWg = 256;
+constexpr uint64_t kGroupBudget = 160ull << 20;  // framebuffer bytes per group
+
+struct DevView {
+    View v;
+    int32_t variant;  // PCR_BASIC / PCR_DEDUP / PCR_HQ
+    uint32_t pad;
+    u64 *fb;          // basic key buffer
+    uint32_t *D;      // HQ depth
+    u64 *S;           // HQ sums
+    uint32_t *out;
+};
+
+struct Group {
+    uint32_t first, count;  // range of the pass's view-index list
+};
+
+// Device table: header, then groups and index lists of both passes, then views.
+struct Header {
+    uint32_t counter[2];  // work queues of pass A and B (zeroed by the clear kernel)
+    uint32_t ngroups[2];
+    uint32_t nviews;
+    uint32_t pad[3];
+};
+
+struct TableLayout {
+    size_t groups[2], index[2], views, bytes;
+};
+
+TableLayout layout(uint32_t cap) {
+    TableLayout L;
+    size_t off = sizeof(Header);
+    for (int p = 0; p < 2; ++p) {
+        L.groups[p] = off;
+        off += sizeof(Group) * cap;
+        L.index[p] = off;
+        off += sizeof(uint32_t) * cap;
+    }
+    off = (off + 63) & ~(size_t)63;
+    L.views = off;
+    off += sizeof(DevView) * cap;
+    L.bytes = (off + 255) & ~(size_t)255;
+    return L;
+}
+
+struct Table {
+    const Header *h;
+    const Group *groups[2];
+    const uint32_t *index[2];
+    const DevView *views;
+};
+
+__device__ __forceinline__ Table table(const unsigned char *base, TableLayout L) {
+    Table t;
+    t.h = (const Header *)base;
+    for (int p = 0; p < 2; ++p) {
+        t.groups[p] = (const Group *)(base + L.groups[p]);
+        t.index[p] = (const uint32_t *)(base + L.index[p]);
+    }
+    t.views = (const DevView *)(base + L.views);
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// Clear and resolve of all views (grid-stride over views x words)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_batch_clear(unsigned char *base, TableLayout L) {
+    Table t = table(base, L);
+    if (blockIdx.x == 0 && threadIdx.x < 2) ((Header *)base)->counter[threadIdx.x] = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint32_t i = 0; i < t.h->nviews; ++i) {
+        const DevView &dv = t.views[i];
+        uint64_t px = (uint64_t)dv.v.W * dv.v.H;
+        if (dv.variant == PCR_HQ) {
+            for (uint64_t k = gid; k < px; k += stride) {
+                dv.D[k] = 0xFFFFFFFFu;
+                dv.S[2 * k] = 0;
+                dv.S[2 * k + 1] = 0;
+            }
+        } else {
+            for (uint64_t k = gid; k < px; k += stride) dv.fb[k] = kEmptyKey;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_batch_resolve(const unsigned char *base, TableLayout L) {
+    Table t = table(base, L);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint32_t i = 0; i < t.h->nviews; ++i) {
+        const DevView &dv = t.views[i];
+        uint64_t px = (uint64_t)dv.v.W * dv.v.H;
+        if (dv.variant == PCR_HQ) {
+            const u32x4 *S = (const u32x4 *)dv.S;
+            for (uint64_t k = gid; k < px; k += stride) {
+                u32x4 s = S[k];  // {G sum, R sum, count, B sum}
+                uint32_t c = s.z, o = 0;
+                if (c != 0)
+                    o = ((s.y / c) & 0xFFu) | ((s.x / c) & 0xFFu) << 8 | ((s.w / c) & 0xFFu) << 16 | 0xFF000000u;
+                dv.out[k] = o;
+            }
+        } else {
+            for (uint64_t k = gid; k < px; k += stride) {
+                u64 key = dv.fb[k];
+                dv.out[k] = key == kEmptyKey ? 0u : (uint32_t)key;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Persistent multi-view passes
+// ---------------------------------------------------------------------------
+constexpr uint32_t kMaxProbeB = 8;
+
+__device__ __forceinline__ void bar_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// LDS: item | count | val[HS] (16 B: min key, or RG and BA sums) | tag[HS] | list[HS]
+struct BLds {
+    uint32_t *item, *count, *tag, *list;
+    u64 *val;  // 2 words per slot
+    uint32_t mask, shift;
+    __device__ BLds(unsigned char *sm, uint32_t hbits) {
+        item = (uint32_t *)sm;
+        count = item + 1;
+        val = (u64 *)(sm + 16);
+        tag = (uint32_t *)(val + 2 * (1u << hbits));
+        list = tag + (1u << hbits);
+        mask = (1u << hbits) - 1u;
+        shift = 32u - hbits;
+    }
+    __device__ __forceinline__ uint32_t slot(uint32_t pid) {
+        uint32_t h = (pid * 0x9E3779B1u) >> shift;
+#pragma unroll 1
+        for (uint32_t probe = 0; probe < kMaxProbeB; ++probe) {
+            uint32_t t = __hip_atomic_load(tag + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (t == pid) return h;
+            if (t == kEmptyPid) {
+                uint32_t old = atomicCAS(tag + h, kEmptyPid, pid);
+                if (old == kEmptyPid) {
+                    list[atomicAdd(count, 1u)] = h;
+                    return h;
+                }
+                if (old == pid) return h;
+            }
+            h = (h + 1u) & mask;
+        }
+        return 0xFFFFFFFFu;
+    }
+};
+
+__device__ __forceinline__ void lmin64(u64 *p, u64 v) {
+    u64 cur = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (v < cur) __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// PASS = 0: closest-point views (64-bit keys) and HQ depth (32-bit depth);
+// PASS = 1: HQ colour sums.
+template <int PPT, int PASS>
+__global__ __launch_bounds__(kBatchWg) void k_batch_pass(const u32x4 *__restrict__ pts, uint64_t n,
+                                                         unsigned char *base, TableLayout L, uint32_t hbits) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    BLds S(smem, hbits);
+    Table t = table(base, L);
+    Header *hdr = (Header *)base;
+    const uint32_t HS = 1u << hbits;
+    const uint32_t T = kBatchWg * PPT;
+    const uint64_t ntiles = (n + T - 1) / T;
+    const uint64_t total = ntiles * t.h->ngroups[PASS];
+    for (uint32_t s = threadIdx.x; s < HS; s += kBatchWg) {
+        S.tag[s] = kEmptyPid;
+        S.val[2 * s] = PASS ? 0ull : kEmptyKey;
+        S.val[2 * s + 1] = 0ull;
+    }
+    if (threadIdx.x == 0) *S.count = 0;
+    for (;;) {
+        bar_lds();
+        if (threadIdx.x == 0) *S.item = atomicAdd(&hdr->counter[PASS], 1u);
+        bar_lds();
+        const uint64_t item = *S.item;
+        if (item >= total) break;  // every workgroup reaches this exit
+        const uint32_t g = (uint32_t)(item / ntiles);
+        const uint64_t tile = item - (uint64_t)g * ntiles;
+        const uint64_t first = tile * T;
+        const uint64_t rem = n - first;
+        u32x4 p[PPT];
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            uint32_t k = (uint32_t)(j * kBatchWg + threadIdx.x);
+            p[j] = load_point(pts + first + (k < rem ? k : (uint32_t)(rem - 1)));
+        }
+        const Group grp = t.groups[PASS][g];
+        for (uint32_t vi = 0; vi < grp.count; ++vi) {
+            const DevView &dv = t.views[t.index[PASS][grp.first + vi]];
+            const View v = dv.v;
+            const bool hq = dv.variant == PCR_HQ;
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) {
+                uint32_t dbits;
+                uint32_t pid = project(v, __uint_as_float(p[j].x), __uint_as_float(p[j].y),
+                                       __uint_as_float(p[j].z), dbits);
+                if ((uint64_t)(j * kBatchWg + threadIdx.x) >= rem) pid = kEmptyPid;
+                if (pid == kEmptyPid) continue;
+                if (PASS == 0) {
+                    u64 val = hq ? (u64)dbits : make_key(dbits, p[j].w);
+                    uint32_t h = S.slot(pid);
+                    if (h != 0xFFFFFFFFu) {
+                        lmin64(S.val + 2 * h, val);
+                    } else if (hq) {
+                        gmin_u32(dv.D + pid, dbits);
+                    } else {
+                        gmin_u64(dv.fb + pid, val);
+                    }
+                } else {
+                    float limit = __uint_as_float(dv.D[pid]) * 1.01f;
+                    if (!(__uint_as_float(dbits) <= limit)) continue;
+                    u64 r = p[j].w & 0xFFu, gg = (p[j].w >> 8) & 0xFFu, bl = (p[j].w >> 16) & 0xFFu;
+                    u64 rg = (r << 32) | gg, ba = (bl << 32) | 1u;
+                    uint32_t h = S.slot(pid);
+                    if (h != 0xFFFFFFFFu) {
+                        __hip_atomic_fetch_add(S.val + 2 * h, rg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        __hip_atomic_fetch_add(S.val + 2 * h + 1, ba, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    } else {
+                        gadd_u64(dv.S + 2 * (u64)pid, rg);
+                        gadd_u64(dv.S + 2 * (u64)pid + 1, ba);
+                    }
+                }
+            }
+            bar_lds();
+            const uint32_t cnt = *S.count;
+            bar_lds();
+            if (threadIdx.x == 0) *S.count = 0;
+            for (uint32_t k = threadIdx.x; k < cnt; k += kBatchWg) {
+                uint32_t h = S.list[k];
+                uint32_t pid = S.tag[h];
+                u64 a = S.val[2 * h], b = S.val[2 * h + 1];
+                S.tag[h] = kEmptyPid;
+                S.val[2 * h] = PASS ? 0ull : kEmptyKey;
+                S.val[2 * h + 1] = 0ull;
+                if (PASS == 0) {
+                    if (hq) {
+                        if ((uint32_t)a < dv.D[pid]) gmin_u32(dv.D + pid, (uint32_t)a);
+                    } else {
+                        gmin_u64(dv.fb + pid, a);
+                    }
+                } else {
+                    gadd_u64(dv.S + 2 * (u64)pid, a);
+                    gadd_u64(dv.S + 2 * (u64)pid + 1, b);
+                }
+            }
+            bar_lds();
+        }
+    }
+}
+
+inline size_t batch_lds(uint32_t hbits) { return 16 + 24ull * (1u << hbits); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+}  // namespace pcr
+
+struct pcr_batch {
+    const pcr::u32x4 *pts = nullptr;
+    uint64_t n = 0;
+    uint32_t capacity = 0;
+    pcr::Shape sh{};
+    uint32_t hbits = 10;
+    pcr::TableLayout lay{};
+    unsigned char *dtable = nullptr;
+    static constexpr int kRing = 4;
+    unsigned char *staging[kRing] = {};
+    hipEvent_t done[kRing] = {};
+    int next = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint32_t grid_pass = 0, grid_io = 0;
+};
+
+namespace pcr {
+namespace {
+
+int launch_pass(pcr_batch *b, int pass, hipStream_t s) {
+    // pass < 0: only raise the kernels' LDS limit (done before graph capture).
+    size_t sm = batch_lds(b->hbits);
+#define PCR_BP(P)                                                                                      \
+    case P:                                                                                            \
+        if (pass < 0) {                                                                                \
+            int rc = allow_lds((const void *)&k_batch_pass<P, 0>, sm);                                 \
+            return rc ? rc : allow_lds((const void *)&k_batch_pass<P, 1>, sm);                         \
+        }                                                                                              \
+        if (pass)                                                                                      \
+            hipLaunchKernelGGL((k_batch_pass<P, 1>), dim3(b->grid_pass), dim3(kBatchWg), sm, s, b->pts, b->n, \
+                               b->dtable, b->lay, b->hbits);                                           \
+        else                                                                                           \
+            hipLaunchKernelGGL((k_batch_pass<P, 0>), dim3(b->grid_pass), dim3(kBatchWg), sm, s, b->pts, b->n, \
+                               b->dtable, b->lay, b->hbits);                                           \
+        break;
+    switch (b->sh.ppt) {
+        PCR_BP(1) PCR_BP(2) PCR_BP(4) PCR_BP(8) PCR_BP(16)
+        default: return fail(PCR_EINVAL, "points per thread %u", b->sh.ppt);
+    }
+#undef PCR_BP
+    PCR_LAUNCHED();
+    return PCR_OK;
+}
+
+int record(pcr_batch *b, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_clear, dim3(b->grid_io), dim3(256), 0, s, b->dtable, b->lay);
+    PCR_LAUNCHED();
+    int rc = launch_pass(b, 0, s);
+    if (rc == PCR_OK) rc = launch_pass(b, 1, s);
+    if (rc != PCR_OK) return rc;
+    hipLaunchKernelGGL(k_batch_resolve, dim3(b->grid_io), dim3(256), 0, s, b->dtable, b->lay);
+    PCR_LAUNCHED();
+    return PCR_OK;
+}
+
+void destroy(pcr_batch *b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (int i = 0; i < pcr_batch::kRing; ++i) {
+        if (b->done[i]) {
+            (void)hipEventSynchronize(b->done[i]);
+            (void)hipEventDestroy(b->done[i]);
+        }
+        if (b->staging[i]) (void)hipHostFree(b->staging[i]);
+    }
+    if (b->dtable) (void)hipFree(b->dtable);
+    delete b;
+}
+
+}  // namespace
+}  // namespace pcr
+
+using namespace pcr;
+
+extern "C" int pcr_batch_create(pcr_batch **plan, const pcr_point *pts, uint64_t n, uint32_t capacity,
+                                const pcr_tune *tune, void *stream) {
+    if (!plan) return fail(PCR_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    if (capacity == 0 || capacity > 4096) return fail(PCR_EINVAL, "capacity %u not in [1, 4096]", capacity);
+    if (n == 0 || !pts || ((uintptr_t)pts & 15)) return fail(PCR_EINVAL, "points must be a non-empty 16-byte aligned device buffer");
+    pcr_tune t{};
+    if (tune) t = *tune;
+    t.wg = kBatchWg;  // the batched kernels are built for 256-thread workgroups
+    Shape sh;
+    int rc = resolve_shape(&t, PCR_DEDUP, sh);
+    if (rc != PCR_OK) return rc;
+    pcr_batch *b = new pcr_batch();
+    b->pts = (const u32x4 *)pts;
+    b->n = n;
+    b->capacity = capacity;
+    b->sh = sh;
+    uint32_t want = sh.slots ? sh.slots : kBatchWg * sh.ppt / 2;
+    b->hbits = 8;
+    while ((1u << b->hbits) < want && b->hbits < 14) ++b->hbits;
+    if (batch_lds(b->hbits) > max_lds()) {
+        destroy(b);
+        return fail(PCR_EINVAL, "%u LDS slots do not fit", 1u << b->hbits);
+    }
+    b->lay = layout(capacity);
+    // Persistent grid: enough workgroups to fill every CU several times over.
+    b->grid_pass = (uint32_t)device_cus() * 8;
+    b->grid_io = (uint32_t)device_cus() * 16;
+    hipError_t e = hipMalloc((void **)&b->dtable, b->lay.bytes);
+    if (e != hipSuccess) {
+        destroy(b);
+        return fail(PCR_ENOMEM, "view table: %s", hipGetErrorString(e));
+    }
+    for (int i = 0; i < pcr_batch::kRing; ++i) {
+        if (hipHostMalloc((void **)&b->staging[i], b->lay.bytes, hipHostMallocDefault) != hipSuccess ||
+            hipEventCreateWithFlags(&b->done[i], hipEventDisableTiming) != hipSuccess) {
+            destroy(b);
+            return fail(PCR_ENOMEM, "staging buffers");
+        }
+        memset(b->staging[i], 0, b->lay.bytes);
+    }
+    // An empty table makes every kernel a no-op; upload it so a graph replay
+    // before the first launch is harmless.
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(b->dtable, b->staging[0], b->lay.bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+        destroy(b);
+        return fail(PCR_EHIP, "plan set-up failed");
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        destroy(b);
+        return fail(PCR_EHIP, "plan set-up failed");
+    }
+    rc = launch_pass(b, -1, nullptr);
+    if (rc != PCR_OK) {
+        destroy(b);
+        return rc;
+    }
+    if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        destroy(b);
+        return fail(PCR_EHIP, "graph capture failed to start");
+    }
+    rc = record(b, b->cap);
+    hipGraph_t g = nullptr;
+    hipError_t ee = hipStreamEndCapture(b->cap, &g);
+    b->graph = g;
+    if (rc != PCR_OK || ee != hipSuccess) {
+        destroy(b);
+        return rc != PCR_OK ? rc : fail(PCR_EHIP, "graph capture failed: %s", hipGetErrorString(ee));
+    }
+    if (hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+        destroy(b);
+        return fail(PCR_EHIP, "graph instantiation failed");
+    }
+    *plan = b;
+    return PCR_OK;
+}
+
+extern "C" int pcr_batch_launch(pcr_batch *b, const pcr_view *views, uint32_t nviews, void *stream) {
+    if (!b) return fail(PCR_EINVAL, "plan is NULL");
+    if (nviews > b->capacity) return fail(PCR_EINVAL, "%u views exceed the plan's capacity %u", nviews, b->capacity);
+    if (nviews > 0 && !views) return fail(PCR_EINVAL, "views is NULL");
+    // Validate and sort views into groups on the host.
+    std::vector<DevView> dv;
+    dv.reserve(nviews);
+    for (uint32_t i = 0; i < nviews; ++i) {
+        const pcr_view &v = views[i];
+        if (v.variant < 0) continue;
+        int rc = check_image(v.w, v.h);
+        if (rc == PCR_OK) rc = check_variant(v.variant & 0xFF);
+        if (rc != PCR_OK) return rc;
+        if (!v.fb || ((uintptr_t)v.fb & 15) || !v.rgba_out || ((uintptr_t)v.rgba_out & 3))
+            return fail(PCR_EINVAL, "view %u: framebuffer must be 16-byte aligned, rgba_out 4-byte aligned", i);
+        DevView d{};
+        d.v = make_view(v.mvp, v.w, v.h);
+        d.variant = v.variant & 0xFF;
+        d.fb = (u64 *)v.fb;
+        d.D = (uint32_t *)v.fb;
+        d.S = (u64 *)((char *)v.fb + hq_depth_bytes(v.w, v.h));
+        d.out = v.rgba_out;
+        dv.push_back(d);
+    }
+    pcr_batch &B = *b;
+    int slot = B.next;
+    B.next = (B.next + 1) % pcr_batch::kRing;
+    PCR_HIP(hipEventSynchronize(B.done[slot]));  // the staging slot's last upload has completed
+    unsigned char *st = B.staging[slot];
+    Header *h = (Header *)st;
+    memset(h, 0, sizeof(Header));
+    h->nviews = (uint32_t)dv.size();
+    memcpy(st + B.lay.views, dv.data(), dv.size() * sizeof(DevView));
+    const uint32_t maxg = B.sh.group ? B.sh.group : 16;
+    for (int pass = 0; pass < 2; ++pass) {
+        Group *gs = (Group *)(st + B.lay.groups[pass]);
+        uint32_t *ix = (uint32_t *)(st + B.lay.index[pass]);
+        uint32_t ng = 0, ni = 0;
+        uint64_t bytes = 0;
+        for (uint32_t i = 0; i < dv.size(); ++i) {
+            bool hq = dv[i].variant == PCR_HQ;
+            if (pass == 1 && !hq) continue;
+            uint64_t fbb = pcr_fb_bytes(dv[i].v.W, dv[i].v.H, dv[i].variant);
+            bool open = ng > 0 && gs[ng - 1].count < maxg && bytes + fbb <= kGroupBudget;
+            if (!open) {
+                gs[ng].first = ni;
+                gs[ng].count = 0;
+                ++ng;
+                bytes = 0;
+            }
+            ix[ni++] = i;
+            gs[ng - 1].count++;
+            bytes += fbb;
+        }
+        h->ngroups[pass] = ng;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    PCR_HIP(hipMemcpyAsync(B.dtable, st, B.lay.bytes, hipMemcpyHostToDevice, s));
+    PCR_HIP(hipGraphLaunch(B.exec, s));
+    PCR_HIP(hipEventRecord(B.done[slot], s));
+    return PCR_OK;
+}
+
+extern "C" int pcr_batch_destroy(pcr_batch *b) {
+    destroy(b);
+    return PCR_OK;
+}

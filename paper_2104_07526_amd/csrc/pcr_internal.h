@@ -22,7 +22,7 @@ typedef unsigned long long u64;
 
 constexpr u64 kEmptyKey = ~0ull;
 constexpr uint32_t kEmptyPid = 0xFFFFFFFFu;
-constexpr uint32_t kFlagMask = PCR_F_EARLYZ | PCR_F_REDUCE | PCR_F_LDS;
+constexpr uint32_t kFlagMask = PCR_F_EARLYZ | PCR_F_REDUCE | PCR_F_LDS | PCR_F_PLAIN;
 constexpr uint32_t kHqPassMask = PCR_F_HQ_DEPTH | PCR_F_HQ_COLOR;
 
 // Camera and viewport of one view, passed by value as a kernel argument (the
@@ -130,6 +130,8 @@ size_t hq_depth_bytes(uint32_t w, uint32_t h);
 
 struct Shape {
     uint32_t ppt, wg, grid;
+    uint32_t group;  // views per point pass (batches)
+    uint32_t slots;  // LDS hash slots of the deduplicating kernels (0 = tile/2)
 };
 int resolve_shape(const pcr_tune *tune, int family, Shape &s);
 

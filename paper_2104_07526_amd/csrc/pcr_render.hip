@@ -63,20 +63,60 @@ __device__ __forceinline__ V lane_pair(V x) {
 
 template <typename V>
 __device__ __forceinline__ bool wave_reduce(uint32_t pid, V val, bool live) {
-    uint64_t lm = __ballot(live);
-    if (lm == 0) return false;
-    uint32_t first = (uint32_t)__builtin_ctzll(lm);
-    uint32_t p0 = __shfl(pid, first, 64);
-    if (__ballot(live && pid == p0) == lm) {
-        V m = wave_min(live ? val : (V)~(V)0);
-        return live && val == m;
+    // Up to two groups: the lanes sharing the first live lane's pixel keep
+    // only their minimum (with every live lane in one group this is the
+    // all-lanes-equal case of Sec. 3.3).
+    const uint32_t lane = __lane_id();
+    uint64_t act = __ballot(live);
+#pragma unroll 1
+    for (int it = 0; it < 2 && act; ++it) {
+        uint32_t leader = (uint32_t)__builtin_ctzll(act);
+        uint32_t p0 = __shfl(pid, leader, 64);
+        uint64_t m = __ballot(live && pid == p0);
+        if (__popcll(m) < 4) break;
+        bool in = (m >> lane) & 1ull;
+        V mv = wave_min(in ? val : (V)~(V)0);
+        if (in) live = val == mv;  // equal keys may all write: harmless
+        act &= ~m;
     }
-    uint32_t ppid = lane_pair(pid);
+    // The remaining lanes: neighbouring pairs merge (Sec. 3.3, pairs).
+    uint32_t ppid = lane_pair(live ? pid : kEmptyPid);
     V pval = lane_pair(val);
-    uint32_t lane = __lane_id();
-    bool same = ppid == pid;  // both live: a culled lane carries kEmptyPid
+    bool same = live && ppid == pid;
     bool lose = same && (pval < val || (pval == val && (lane & 1)));
     return live && !lose;
+}
+
+// Sums of the HQ colour pass: lanes that share the first live lane's pixel
+// hand their (r<<32|g, b<<32|1) words to that lane (the all-lanes-equal
+// reduction of Sec. 3.3 applied to integer sums; exact because + commutes),
+// for up to two leaders per wavefront.  Must be called by the whole wave.
+__device__ __forceinline__ void wave_group_sums(uint32_t pid, u64 &rg, u64 &ba, bool &live) {
+    const uint32_t lane = __lane_id();
+    uint64_t act = __ballot(live);
+#pragma unroll 1
+    for (int it = 0; it < 2 && act; ++it) {
+        uint32_t leader = (uint32_t)__builtin_ctzll(act);
+        uint32_t p0 = __shfl(pid, leader, 64);
+        uint64_t m = __ballot(live && pid == p0);
+        if (__popcll(m) < 4) break;
+        bool in = (m >> lane) & 1ull;
+        u64 a = in ? rg : 0ull, b = in ? ba : 0ull;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            a += __shfl_xor(a, o, 64);
+            b += __shfl_xor(b, o, 64);
+        }
+        if (in) {
+            if (lane == leader) {
+                rg = a;
+                ba = b;
+            } else {
+                live = false;
+            }
+        }
+        act &= ~m;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -89,6 +129,9 @@ __device__ __forceinline__ bool wave_reduce(uint32_t pid, V val, bool live) {
 struct Sum2 {
     u64 rg, ba;
 };
+
+constexpr uint32_t kMaxProbe = 8;
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
 
 template <typename V>
 struct Lds {
@@ -108,11 +151,13 @@ struct Lds {
     }
 
     // Slot of pixel `pid`, claimed if new (then appended to the list of the
-    // tile with parity `par`).  The table is at most half full, so the probe
-    // sequence always reaches the pixel's slot or a free one.
+    // tile with parity `par`), or kNoSlot when kMaxProbe slots in a row are
+    // taken by other pixels -- the caller then updates the framebuffer
+    // directly, which is always correct because min and + commute.
     __device__ __forceinline__ uint32_t slot(uint32_t pid, uint32_t par) {
         uint32_t h = (pid * 0x9E3779B1u) >> shift;
-        for (;;) {
+#pragma unroll 1
+        for (uint32_t probe = 0; probe < kMaxProbe; ++probe) {
             uint32_t t = __hip_atomic_load(tag + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (t == pid) return h;
             if (t == kEmptyPid) {
@@ -125,16 +170,28 @@ struct Lds {
             }
             h = (h + 1u) & mask;
         }
+        return kNoSlot;
     }
 };
 
-inline size_t lds_bytes(uint32_t T, uint32_t hbits, size_t vbytes) {
-    return 16 + ((size_t)vbytes + 4) * (1u << hbits) + 4ull * T;
+// Workgroup barrier that orders LDS only: outstanding global loads, stores
+// and atomics stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-inline uint32_t lds_hbits(uint32_t T) {
-    uint32_t b = 1;
-    while ((1u << b) < 2u * T) ++b;  // at most half full
+inline size_t lds_bytes(uint32_t hbits, size_t vbytes) {
+    return 16 + ((size_t)vbytes + 8) * (1u << hbits);
+}
+
+// Table of about T/2 slots for a tile of T points (at least 256): tiles with
+// more distinct pixels overflow into direct updates.
+inline uint32_t lds_hbits(uint32_t T, uint32_t group) {
+    uint32_t want = group ? group : T / 2;
+    uint32_t b = 8;
+    while ((1u << b) < want && b < 15) ++b;
     return b;
 }
 
@@ -151,13 +208,24 @@ struct Tiles {
     }
 };
 
+// Tile load.  The tile's first point is uniform across the workgroup, so full
+// tiles use a scalar base plus a 32-bit lane offset and issue all PPT loads
+// back to back before the first use; in the last, partial tile indices past
+// the end are clamped to the last point (the caller discards those lanes).
 template <int PPT>
-__device__ __forceinline__ void load_tile(const u32x4 *__restrict__ pts, uint64_t base, uint32_t wg,
+__device__ __forceinline__ void load_tile(const u32x4 *__restrict__ pts, uint64_t first, uint32_t wg,
                                           uint64_t n, u32x4 (&p)[PPT]) {
+    const u32x4 *tp = pts + first;
+    const uint64_t rem = n - first;
+    if (rem >= (uint64_t)wg * PPT) {
 #pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-        uint64_t i = base + (uint64_t)j * wg;
-        p[j] = i < n ? load_point(pts + i) : u32x4{0u, 0u, 0u, 0u};
+        for (int j = 0; j < PPT; ++j) p[j] = load_point(tp + (uint32_t)(j * wg + threadIdx.x));
+    } else {
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            uint32_t k = (uint32_t)(j * wg + threadIdx.x);
+            p[j] = load_point(tp + (k < rem ? k : (uint32_t)(rem - 1)));
+        }
     }
 }
 
@@ -170,9 +238,10 @@ __global__ __launch_bounds__(1024) void k_basic(const u32x4 *__restrict__ pts, T
     for (uint64_t b = blockIdx.x; b < tl.nblocks; b += gridDim.x) {
         uint64_t t;
         if (!tl.tile(b, t)) continue;
-        uint64_t base = t * wg * PPT + threadIdx.x;
+        const uint64_t first = t * wg * PPT;
+        const uint64_t base = first + threadIdx.x;
         u32x4 p[PPT];
-        load_tile<PPT>(pts, base, wg, tl.n, p);
+        load_tile<PPT>(pts, first, wg, tl.n, p);
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             uint32_t dbits;
@@ -190,6 +259,15 @@ __global__ __launch_bounds__(1024) void k_basic(const u32x4 *__restrict__ pts, T
 
 // Closest-point render with LDS deduplication (Sec. 3.4); V = u64 keys for the
 // basic framebuffer, V = uint32 depth bits for the HQ depth pass (Sec. 3.5).
+template <typename V>
+__device__ __forceinline__ void direct_min(V *fb, uint32_t pid, V val, bool earlyz) {
+    if constexpr (sizeof(V) == 8) {
+        if (!earlyz || val < peek_u64(fb + pid)) gmin_u64(fb + pid, val);
+    } else {
+        if (!earlyz || val < peek_u32(fb + pid)) gmin_u32(fb + pid, val);
+    }
+}
+
 template <typename V, int PPT, bool EARLYZ, bool REDUCE>
 __global__ __launch_bounds__(1024) void k_dedup(const u32x4 *__restrict__ pts, Tiles tl, View v,
                                                 V *__restrict__ fb, uint32_t hbits) {
@@ -202,14 +280,15 @@ __global__ __launch_bounds__(1024) void k_dedup(const u32x4 *__restrict__ pts, T
         L.val[s] = (V)~(V)0;
     }
     if (threadIdx.x < 2) L.count[threadIdx.x] = 0;
-    __syncthreads();
+    lds_barrier();
     uint32_t par = 0;
     for (uint64_t b = blockIdx.x; b < tl.nblocks; b += gridDim.x) {
         uint64_t t;
         if (!tl.tile(b, t)) continue;
-        uint64_t base = t * wg * PPT + threadIdx.x;
+        const uint64_t first = t * wg * PPT;
+        const uint64_t base = first + threadIdx.x;
         u32x4 p[PPT];
-        load_tile<PPT>(pts, base, wg, tl.n, p);
+        load_tile<PPT>(pts, first, wg, tl.n, p);
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             uint32_t dbits;
@@ -225,10 +304,19 @@ __global__ __launch_bounds__(1024) void k_dedup(const u32x4 *__restrict__ pts, T
             if (REDUCE) w = wave_reduce<V>(pid, val, w);
             if (w) {
                 uint32_t h = L.slot(pid, par);
-                __hip_atomic_fetch_min(L.val + h, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (h != kNoSlot) {
+                    // Early test against the slot (its value only decreases):
+                    // lanes that cannot lower it skip the atomic, which keeps
+                    // many lanes hitting one slot from serialising.
+                    V cur = __hip_atomic_load(L.val + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (val < cur)
+                        __hip_atomic_fetch_min(L.val + h, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                } else {
+                    direct_min<V>(fb, pid, val, EARLYZ);
+                }
             }
         }
-        __syncthreads();
+        lds_barrier();
         uint32_t cnt = L.count[par];
         if (threadIdx.x == 0) L.count[par ^ 1u] = 0;
         for (uint32_t k = threadIdx.x; k < cnt; k += wg) {
@@ -237,16 +325,9 @@ __global__ __launch_bounds__(1024) void k_dedup(const u32x4 *__restrict__ pts, T
             V val = L.val[h];
             L.tag[h] = kEmptyPid;
             L.val[h] = (V)~(V)0;
-            bool w = true;
-            if constexpr (sizeof(V) == 8) {
-                if (EARLYZ) w = val < peek_u64(fb + pid);
-                if (w) gmin_u64(fb + pid, val);
-            } else {
-                if (EARLYZ) w = val < peek_u32(fb + pid);
-                if (w) gmin_u32(fb + pid, val);
-            }
+            direct_min<V>(fb, pid, val, EARLYZ);
         }
-        __syncthreads();
+        lds_barrier();
         par ^= 1u;
     }
 }
@@ -259,9 +340,10 @@ __global__ __launch_bounds__(1024) void k_hq_depth(const u32x4 *__restrict__ pts
     for (uint64_t b = blockIdx.x; b < tl.nblocks; b += gridDim.x) {
         uint64_t t;
         if (!tl.tile(b, t)) continue;
-        uint64_t base = t * wg * PPT + threadIdx.x;
+        const uint64_t first = t * wg * PPT;
+        const uint64_t base = first + threadIdx.x;
         u32x4 p[PPT];
-        load_tile<PPT>(pts, base, wg, tl.n, p);
+        load_tile<PPT>(pts, first, wg, tl.n, p);
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             uint32_t dbits;
@@ -297,35 +379,44 @@ __global__ __launch_bounds__(1024) void k_hq_color(const u32x4 *__restrict__ pts
             L.val[s].ba = 0;
         }
         if (threadIdx.x < 2) L.count[threadIdx.x] = 0;
-        __syncthreads();
+        lds_barrier();
     }
     uint32_t par = 0;
     for (uint64_t b = blockIdx.x; b < tl.nblocks; b += gridDim.x) {
         uint64_t t;
         if (!tl.tile(b, t)) continue;
-        uint64_t base = t * wg * PPT + threadIdx.x;
+        const uint64_t first = t * wg * PPT;
+        const uint64_t base = first + threadIdx.x;
         u32x4 p[PPT];
-        load_tile<PPT>(pts, base, wg, tl.n, p);
+        load_tile<PPT>(pts, first, wg, tl.n, p);
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             uint32_t dbits;
             uint32_t pid = project(v, __uint_as_float(p[j].x), __uint_as_float(p[j].y),
                                    __uint_as_float(p[j].z), dbits);
             if (base + (uint64_t)j * wg >= tl.n) pid = kEmptyPid;
-            if (pid == kEmptyPid || !hq_contributes(D, pid, dbits)) continue;
+            bool live = pid != kEmptyPid;
+            if (live) live = hq_contributes(D, pid, dbits);
             u64 r = p[j].w & 0xFFu, g = (p[j].w >> 8) & 0xFFu, bl = (p[j].w >> 16) & 0xFFu;
             u64 rg = (r << 32) | g, ba = (bl << 32) | 1u;
+            wave_group_sums(pid, rg, ba, live);
+            if (!live) continue;
             if (!LDS) {
                 gadd_u64(S + 2 * (u64)pid, rg);
                 gadd_u64(S + 2 * (u64)pid + 1, ba);
                 continue;
             }
             uint32_t h = L.slot(pid, par);
+            if (h == kNoSlot) {
+                gadd_u64(S + 2 * (u64)pid, rg);
+                gadd_u64(S + 2 * (u64)pid + 1, ba);
+                continue;
+            }
             __hip_atomic_fetch_add(&L.val[h].rg, rg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             __hip_atomic_fetch_add(&L.val[h].ba, ba, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         if (!LDS) continue;
-        __syncthreads();
+        lds_barrier();
         uint32_t cnt = L.count[par];
         if (threadIdx.x == 0) L.count[par ^ 1u] = 0;
         for (uint32_t k = threadIdx.x; k < cnt; k += wg) {
@@ -338,7 +429,7 @@ __global__ __launch_bounds__(1024) void k_hq_color(const u32x4 *__restrict__ pts
             gadd_u64(S + 2 * (u64)pid, sm.rg);
             gadd_u64(S + 2 * (u64)pid + 1, sm.ba);
         }
-        __syncthreads();
+        lds_barrier();
         par ^= 1u;
     }
 }
@@ -425,8 +516,8 @@ struct BasicL {
         bool ez = L.flags & PCR_F_EARLYZ, rd = L.flags & PCR_F_REDUCE;
         u64 *fb = (u64 *)L.fb;
         if (L.flags & PCR_F_LDS) {
-            uint32_t T = L.sh.wg * P, hb = lds_hbits(T);
-            size_t sm = lds_bytes(T, hb, 8);
+            uint32_t T = L.sh.wg * P, hb = lds_hbits(T, L.sh.slots);
+            size_t sm = lds_bytes(hb, 8);
             if (sm > max_lds())
                 return fail(PCR_EINVAL, "tile of %u points needs %zu bytes of LDS", T, sm);
 #define PCR_DD(E, R)                                                                                    \
@@ -460,8 +551,8 @@ struct DepthL {
         bool ez = L.flags & PCR_F_EARLYZ;
         uint32_t *D = (uint32_t *)L.fb;
         if (L.flags & PCR_F_LDS) {
-            uint32_t T = L.sh.wg * P, hb = lds_hbits(T);
-            size_t sm = lds_bytes(T, hb, 4);
+            uint32_t T = L.sh.wg * P, hb = lds_hbits(T, L.sh.slots);
+            size_t sm = lds_bytes(hb, 4);
             if (sm > max_lds())
                 return fail(PCR_EINVAL, "tile of %u points needs %zu bytes of LDS", T, sm);
             int rc = allow_lds(ez ? (const void *)&k_dedup<uint32_t, P, true, false>
@@ -491,8 +582,8 @@ struct ColorL {
         const uint32_t *D = (const uint32_t *)L.fb;
         u64 *S = (u64 *)((char *)L.fb + hq_depth_bytes(w, h));
         if (L.flags & PCR_F_LDS) {
-            uint32_t T = L.sh.wg * P, hb = lds_hbits(T);
-            size_t sm = lds_bytes(T, hb, 16);
+            uint32_t T = L.sh.wg * P, hb = lds_hbits(T, L.sh.slots);
+            size_t sm = lds_bytes(hb, 16);
             if (sm > max_lds())
                 return fail(PCR_EINVAL, "tile of %u points needs %zu bytes of LDS", T, sm);
             if (int rc = allow_lds((const void *)&k_hq_color<P, true>, sm)) return rc;
@@ -558,19 +649,19 @@ extern "C" int pcr_render_ex(const pcr_point *pts, uint64_t n, const float mvp[1
     rc = resolve_shape(tune, fam, sh);
     if (rc != PCR_OK) return rc;
     if (n == 0) return PCR_OK;
-    Launch L{(const u32x4 *)pts, n, make_view(mvp, w, h), fb, sh, flags, (hipStream_t)stream};
+    Launch L{(const u32x4 *)pts, n, make_view(mvp, w, h), fb, sh, flags & ~PCR_F_PLAIN, (hipStream_t)stream};
+    const bool chosen = (flags & kFlagMask) != 0;
     if (fam == PCR_BASIC) return render_basic(L);
     if (fam == PCR_DEDUP) {
-        if ((flags & kFlagMask) == 0) L.flags |= PCR_F_EARLYZ | PCR_F_LDS;
+        if (!chosen) L.flags |= PCR_F_LDS | PCR_F_REDUCE;
         return render_basic(L);
     }
-    // PCR_HQ
+    // PCR_HQ: depth pass, then colour pass.
+    if (!chosen) L.flags |= PCR_F_LDS;
     uint32_t pass = flags & kHqPassMask;
     if (pass == 0) pass = kHqPassMask;
     if (pass & PCR_F_HQ_DEPTH) {
-        Launch d = L;
-        if ((flags & kFlagMask) == 0) d.flags |= PCR_F_EARLYZ;
-        rc = render_hq_depth(d);
+        rc = render_hq_depth(L);
         if (rc != PCR_OK) return rc;
     }
     if (pass & PCR_F_HQ_COLOR) rc = render_hq_color(L, w, h);

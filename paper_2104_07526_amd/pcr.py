@@ -24,6 +24,7 @@ BASIC, DEDUP, HQ = 0, 1, 2
 F_EARLYZ = 1 << 8
 F_REDUCE = 1 << 9
 F_LDS = 1 << 10
+F_PLAIN = 1 << 11
 F_HQ_DEPTH = 1 << 12
 F_HQ_COLOR = 1 << 13
 ORDER_MORTON, ORDER_MORTON_SHUFFLE, ORDER_SHUFFLE = 0, 1, 2
@@ -42,7 +43,7 @@ class PcrError(RuntimeError):
 
 class Tune(ctypes.Structure):
     _fields_ = [("ppt", ctypes.c_uint32), ("wg", ctypes.c_uint32), ("grid", ctypes.c_uint32),
-                ("group", ctypes.c_uint32)]
+                ("group", ctypes.c_uint32), ("slots", ctypes.c_uint32)]
 
 
 class View(ctypes.Structure):
@@ -122,7 +123,7 @@ def _tune(t):
     if isinstance(t, Tune):
         return ctypes.byref(t)
     return ctypes.byref(Tune(int(t.get("ppt", 0)), int(t.get("wg", 0)), int(t.get("grid", 0)),
-                             int(t.get("group", 0))))
+                             int(t.get("group", 0)), int(t.get("slots", 0))))
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,282 @@
+"""Continuous-batching render server over resident point clouds.
+
+Requests (cloud, camera, resolution, variant) arrive at any time.  The
+scheduler admits them in arrival order while their framebuffers fit the
+framebuffer memory budget, and launches, for every cloud with admitted work
+and a free batch slot, one batched multi-view render of everything admitted
+for that cloud so far.  Each cloud has two batch plans on two streams, so a
+new batch of a cloud starts while its previous batch is still on the GPU, and
+batches of different clouds overlap on the device.  A request's image is the
+same as rendering it alone (integer min / sum updates).
+
+The scheduler is independent of the device: a backend supplies buffer sizes,
+batch launches and completion queries.  ``GpuBackend`` drives libpcr batch
+plans; tests drive the scheduler with their own backends.
+"""
+from __future__ import annotations
+
+import bisect
+import dataclasses
+import threading
+import time
+from concurrent.futures import Future
+
+import numpy as np
+
+from . import pcr
+
+ALIGN = 256
+
+
+def _align(n: int) -> int:
+    return (n + ALIGN - 1) // ALIGN * ALIGN
+
+
+@dataclasses.dataclass
+class Request:
+    cloud: int
+    mvp: np.ndarray
+    w: int
+    h: int
+    variant: int
+    arrival: float = 0.0            # time.perf_counter() seconds
+    rid: int = -1
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    image: object                   # device tensor (GPU backend) or array
+    arrival: float
+    launched: float
+    finished: float
+    batch_size: int
+    status: str = "ok"
+    error: str = ""
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class Arena:
+    """First-fit allocator of byte ranges inside one preallocated region
+    (framebuffer memory budget).  Host bookkeeping only."""
+
+    def __init__(self, size: int):
+        self.size = size
+        self.free = [(0, size)]      # sorted (offset, length), coalesced
+        self.used = 0
+
+    def alloc(self, n: int):
+        n = _align(max(n, 1))
+        for i, (off, ln) in enumerate(self.free):
+            if ln >= n:
+                if ln == n:
+                    self.free.pop(i)
+                else:
+                    self.free[i] = (off + n, ln - n)
+                self.used += n
+                return off
+        return None
+
+    def release(self, off: int, n: int):
+        n = _align(max(n, 1))
+        self.used -= n
+        i = bisect.bisect_left(self.free, (off, 0))
+        self.free.insert(i, (off, n))
+        # coalesce with neighbours
+        if i + 1 < len(self.free) and self.free[i][0] + self.free[i][1] == self.free[i + 1][0]:
+            self.free[i] = (self.free[i][0], self.free[i][1] + self.free[i + 1][1])
+            self.free.pop(i + 1)
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] == self.free[i][0]:
+            self.free[i - 1] = (self.free[i - 1][0], self.free[i - 1][1] + self.free[i][1])
+            self.free.pop(i)
+
+
+class GpuBackend:
+    """libpcr batch plans on torch streams.  Framebuffers are carved from one
+    device arena (the admission budget); each request's image is its own
+    device tensor, written directly by the batch's resolve."""
+
+    def __init__(self, clouds, budget_bytes: int, capacity: int = 16, plans_per_cloud: int = 2,
+                 tune=None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.clouds = clouds
+        self.capacity = capacity
+        self.arena_mem = torch.empty(budget_bytes, dtype=torch.uint8, device=device)
+        self.base = self.arena_mem.data_ptr()
+        self.slots = []              # per cloud: [plan, stream, event or None]
+        for c in clouds:
+            row = []
+            for _ in range(plans_per_cloud):
+                s = torch.cuda.Stream(device=device)
+                row.append([pcr.BatchPlan(c, capacity, tune=tune, stream=s), s, None])
+            self.slots.append(row)
+        self.points = [pcr._npoints(c) for c in clouds]
+
+    def bytes_for(self, req: Request) -> int:
+        return _align(pcr.fb_bytes(req.w, req.h, req.variant))
+
+    def new_image(self, req: Request):
+        return self.torch.empty(req.w * req.h, dtype=self.torch.int32, device=self.device)
+
+    def free_slot(self, cloud: int):
+        for i, sl in enumerate(self.slots[cloud]):
+            if sl[2] is None:
+                return i
+        return None
+
+    def launch(self, cloud: int, slot: int, reqs, offsets, images):
+        plan, stream, _ = self.slots[cloud][slot]
+        views = [pcr.make_view(r.mvp, r.w, r.h, r.variant, self.base + off, img)
+                 for r, off, img in zip(reqs, offsets, images)]
+        for img in images:
+            img.record_stream(stream)
+        plan.launch(views, stream=stream)
+        ev = self.torch.cuda.Event()
+        ev.record(stream)
+        self.slots[cloud][slot][2] = ev
+        return (cloud, slot)
+
+    def done(self, handle) -> bool:
+        cloud, slot = handle
+        ev = self.slots[cloud][slot][2]
+        return ev is None or ev.query()
+
+    def retire(self, handle):
+        cloud, slot = handle
+        self.slots[cloud][slot][2] = None
+
+    def close(self):
+        for row in self.slots:
+            for sl in row:
+                sl[0].close()
+
+
+class Server:
+    """Continuous-batching scheduler (see the module docstring).
+
+    submit() may be called from any thread; results are delivered through
+    futures.  With ``run_inline`` the caller drives the loop (step())."""
+
+    def __init__(self, backend, budget_bytes: int, max_batch: int | None = None, poll_s: float = 2e-5):
+        self.be = backend
+        self.arena = Arena(budget_bytes)
+        self.max_batch = max_batch or backend.capacity
+        self.poll_s = poll_s
+        self.lock = threading.Lock()
+        self.incoming = []            # (request, future) not yet admitted, arrival order
+        self.admitted = {}            # cloud -> list of (request, future, offset, image)
+        self.inflight = []            # (handle, [(request, future, offset, image)], launched)
+        self.next_id = 0
+        self.completed = 0
+        self.rejected = 0
+        self._stop = False
+        self._thread = None
+
+    # -- client side ----------------------------------------------------------
+    def submit(self, req: Request) -> Future:
+        fut = Future()
+        with self.lock:
+            req.rid = self.next_id
+            self.next_id += 1
+            if req.arrival == 0.0:
+                req.arrival = time.perf_counter()
+            need = self.be.bytes_for(req)
+            if need > self.arena.size or not (0 <= req.cloud < len(self.be.points)):
+                self.rejected += 1
+                fut.set_result(Result(req.rid, None, req.arrival, 0.0, time.perf_counter(), 0, "rejected",
+                                      "request does not fit the framebuffer budget" if need > self.arena.size
+                                      else "unknown cloud"))
+                return fut
+            self.incoming.append((req, fut))
+        return fut
+
+    # -- scheduler ------------------------------------------------------------
+    def _admit(self):
+        with self.lock:
+            keep = []
+            blocked = False
+            for req, fut in self.incoming:
+                if fut.cancelled():
+                    continue
+                off = None if blocked else self.arena.alloc(self.be.bytes_for(req))
+                if off is None:
+                    blocked = True     # arrival order: later requests wait behind it
+                    keep.append((req, fut))
+                    continue
+                self.admitted.setdefault(req.cloud, []).append((req, fut, off, self.be.new_image(req)))
+            self.incoming = keep
+
+    def _launch(self):
+        for cloud, items in list(self.admitted.items()):
+            if not items:
+                continue
+            slot = self.be.free_slot(cloud)
+            if slot is None:
+                continue
+            take, rest = items[: self.max_batch], items[self.max_batch:]
+            self.admitted[cloud] = rest
+            now = time.perf_counter()
+            try:
+                h = self.be.launch(cloud, slot, [t[0] for t in take], [t[2] for t in take],
+                                   [t[3] for t in take])
+            except Exception as e:  # a failed launch fails its requests; the server goes on
+                for req, fut, off, _ in take:
+                    self.arena.release(off, self.be.bytes_for(req))
+                    fut.set_result(Result(req.rid, None, req.arrival, now, time.perf_counter(), len(take),
+                                          "error", str(e)))
+                continue
+            self.inflight.append((h, take, now))
+
+    def _complete(self):
+        still = []
+        for h, take, launched in self.inflight:
+            if not self.be.done(h):
+                still.append((h, take, launched))
+                continue
+            fin = time.perf_counter()
+            self.be.retire(h)
+            for req, fut, off, img in take:
+                self.arena.release(off, self.be.bytes_for(req))
+                self.completed += 1
+                fut.set_result(Result(req.rid, img, req.arrival, launched, fin, len(take)))
+        self.inflight = still
+
+    def step(self) -> bool:
+        """One scheduler iteration; True while work is pending."""
+        self._complete()
+        self._admit()
+        self._launch()
+        with self.lock:
+            pending = bool(self.incoming) or any(self.admitted.values())
+        return pending or bool(self.inflight)
+
+    def drain(self, timeout_s: float = 60.0):
+        t0 = time.perf_counter()
+        while self.step():
+            if time.perf_counter() - t0 > timeout_s:
+                raise TimeoutError("server did not drain")
+            time.sleep(self.poll_s)
+
+    def start(self):
+        def loop():
+            while not self._stop:
+                busy = self.step()
+                if not busy:
+                    time.sleep(self.poll_s)
+        self._thread = threading.Thread(target=loop, daemon=True)
+        self._thread.start()
+
+    def stop(self):
+        self._stop = True
+        if self._thread:
+            self._thread.join()
+        self.drain()
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else float("nan")

@@ -1,0 +1,108 @@
+"""The C ABI without a GPU: the library loads, exports every entry point that
+include/pcr.h declares, and rejects bad arguments on the host before any HIP
+call.  No compute call is made here."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2104_07526_amd import pcr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pcr.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pcr_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for n in ("pcr_fb_bytes", "pcr_fb_clear", "pcr_render", "pcr_render_ex", "pcr_resolve",
+              "pcr_reorder_scratch_bytes", "pcr_reorder", "pcr_batch_create", "pcr_batch_launch",
+              "pcr_batch_destroy", "pcr_last_error", "pcr_version"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pcr.lib()
+    for n in declared():
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", pcr.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (pcr_\w+)", out))
+    assert set(declared()) <= exported
+
+
+def test_header_compiles_as_c():
+    src = '#include "pcr.h"\nint main(void){ pcr_point p; (void)p; return (int)sizeof(pcr_point) - 16; }\n'
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.dirname(HEADER), "-x", "c", "-",
+                        "-o", "/dev/null"], input=src, text=True, capture_output=True)
+    assert r.returncode == 0, r.stderr
+
+
+def test_fb_bytes():
+    assert pcr.fb_bytes(1920, 1080, pcr.BASIC) == 8 * 1920 * 1080
+    assert pcr.fb_bytes(1920, 1080, pcr.DEDUP | pcr.F_LDS) == 8 * 1920 * 1080
+    d = (4 * 1920 * 1080 + 255) // 256 * 256
+    assert pcr.fb_bytes(1920, 1080, pcr.HQ) == d + 16 * 1920 * 1080
+    assert pcr.fb_bytes(3, 1, pcr.HQ) == 256 + 48
+    for bad in [(0, 5, 0), (5, 0, 0), (1 << 24, 1, 0), (70000, 70000, 0), (4, 4, 7), (4, 4, pcr.BASIC | pcr.F_HQ_DEPTH)]:
+        assert pcr.fb_bytes(*bad) == 0, bad
+
+
+@pytest.mark.parametrize("variant,msg", [
+    (3, "unknown variant"),
+    (pcr.BASIC | (1 << 20), "flag bits"),
+    (pcr.HQ | pcr.F_REDUCE, "flag bits"),
+    (pcr.DEDUP | pcr.F_PLAIN | pcr.F_LDS, "PLAIN"),
+])
+def test_render_rejects_bad_variants(variant, msg):
+    m = (ctypes.c_float * 16)()
+    rc = pcr.lib().pcr_render(None, 0, m, 4, 4, variant, None, None)
+    assert rc == pcr.EINVAL
+    assert msg in pcr.lib().pcr_last_error().decode()
+
+
+def test_render_rejects_bad_pointers_and_sizes():
+    L = pcr.lib()
+    m = (ctypes.c_float * 16)()
+    assert L.pcr_render(None, 0, m, 0, 4, 0, 16, None) == pcr.EINVAL
+    assert L.pcr_render(None, 10, m, 4, 4, 0, 16, None) == pcr.EINVAL          # null points
+    assert L.pcr_render(8, 10, m, 4, 4, 0, 16, None) == pcr.EINVAL             # misaligned points
+    assert L.pcr_render(16, 10, m, 4, 4, 0, 8, None) == pcr.EINVAL             # misaligned fb
+    assert L.pcr_render(16, 10, None, 4, 4, 0, 16, None) == pcr.EINVAL         # null mvp
+    tune = pcr.Tune(3, 256, 0, 0, 0)
+    assert L.pcr_render_ex(16, 10, m, 4, 4, 0, 16, ctypes.byref(tune), None) == pcr.EINVAL
+    tune = pcr.Tune(4, 96, 0, 0, 0)
+    assert L.pcr_render_ex(16, 10, m, 4, 4, 0, 16, ctypes.byref(tune), None) == pcr.EINVAL
+    assert L.pcr_resolve(16, 4, 4, 0, None, None) == pcr.EINVAL
+    assert L.pcr_fb_clear(None, 4, 4, 0, None) == pcr.EINVAL
+
+
+def test_reorder_argument_checks():
+    L = pcr.lib()
+    assert L.pcr_reorder_scratch_bytes(1000, 5, 128) == 0
+    assert L.pcr_reorder_scratch_bytes(1000, pcr.ORDER_MORTON_SHUFFLE, 0) == 0
+    assert L.pcr_reorder_scratch_bytes(1 << 32, pcr.ORDER_MORTON, 128) == 0
+    a = L.pcr_reorder_scratch_bytes(1000, pcr.ORDER_MORTON, 128)
+    b = L.pcr_reorder_scratch_bytes(1000, pcr.ORDER_MORTON_SHUFFLE, 128)
+    assert 0 < a < b
+    assert L.pcr_reorder(16, 16 * 2000, None, 1000, 9, 128, 0, 256, a, None) == pcr.EINVAL
+    assert L.pcr_reorder(16, 16 * 2000, None, 1 << 32, 0, 128, 0, 256, a, None) == pcr.EINVAL
+    assert L.pcr_reorder(16, 32, None, 1000, 0, 128, 0, 256, a, None) == pcr.EINVAL     # overlap
+    assert L.pcr_reorder(16, 16 * 2000, None, 1000, 0, 128, 0, 256, a - 1, None) == pcr.ENOMEM
+    assert L.pcr_reorder(16, 16 * 2000, None, 0, 0, 128, 0, 0, 0, None) == pcr.OK       # n == 0
+
+
+def test_batch_argument_checks():
+    L = pcr.lib()
+    h = ctypes.c_void_p()
+    assert L.pcr_batch_create(ctypes.byref(h), 16, 100, 0, None, None) == pcr.EINVAL
+    assert L.pcr_batch_create(ctypes.byref(h), 8, 100, 4, None, None) == pcr.EINVAL
+    assert L.pcr_batch_create(ctypes.byref(h), 16, 0, 4, None, None) == pcr.EINVAL
+    assert L.pcr_batch_launch(None, None, 0, None) == pcr.EINVAL
+    assert L.pcr_batch_destroy(None) == pcr.OK

@@ -1,0 +1,116 @@
+"""Batched multi-view plans (one hipGraph replay per launch): every view equals
+the oracle's render of that view alone and the single-view GPU render, on
+repeated replays with eager work in between."""
+import numpy as np
+import pytest
+
+from gpu_util import assert_same_fb, oracle_frame, read_fb, render_frame, upload
+from paper_2104_07526_amd import pcr, synth
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(96, 54), (160, 90), (64, 64), (200, 120)]
+
+
+def make_views(k, seed, variants=(pcr.BASIC, pcr.DEDUP, pcr.HQ)):
+    poses = synth.random_poses(k, seed=seed)
+    out = []
+    for i, (eye, tgt, up) in enumerate(poses):
+        W, H = SIZES[i % len(SIZES)]
+        out.append((synth.mvp(eye, tgt, up, W, H), W, H, variants[i % len(variants)]))
+    return out
+
+
+def run_batch(plan, views):
+    import torch
+    bufs, pv = [], []
+    for m, W, H, var in views:
+        fb = pcr.alloc_fb(W, H, var)
+        img = torch.empty(W * H, dtype=torch.int32, device="cuda")
+        bufs.append((fb, img))
+        pv.append(pcr.make_view(m, W, H, var, fb, img))
+    plan.launch(pv)
+    torch.cuda.synchronize()
+    return bufs
+
+
+@pytest.fixture(scope="module")
+def scene():
+    pts = synth.terrain_and_buildings(300_000, 100_000, seed=5)
+    return pts, upload(pts)
+
+
+@pytest.mark.parametrize("tune", [None, {"ppt": 4}, {"ppt": 8, "group": 2}, {"ppt": 16, "slots": 256}])
+def test_views_match_oracle(orc, scene, tune):
+    pts, d = scene
+    views = make_views(9, seed=11)
+    plan = pcr.BatchPlan(d, capacity=12, tune=tune)
+    bufs = run_batch(plan, views)
+    for (m, W, H, var), (fb, img) in zip(views, bufs):
+        efb, eimg = oracle_frame(orc, pts, m, W, H, var)
+        assert_same_fb(read_fb(fb, W, H, var), efb, var)
+        assert np.array_equal(img.cpu().numpy().view(np.uint32), eimg)
+    plan.close()
+
+
+def test_replays_with_eager_work_between(orc, scene):
+    """The graph is replayed with new views each time; eager single-view
+    renders run between the replays; every replay is checked."""
+    pts, d = scene
+    plan = pcr.BatchPlan(d, capacity=6)
+    for rep in range(4):
+        views = make_views(5 + rep % 2, seed=100 + rep)
+        bufs = run_batch(plan, views)
+        m0, W0, H0, v0 = views[0]
+        _, eager = render_frame(d, m0, W0, H0, v0)
+        for (m, W, H, var), (fb, img) in zip(views, bufs):
+            _, eimg = oracle_frame(orc, pts, m, W, H, var)
+            assert np.array_equal(img.cpu().numpy().view(np.uint32), eimg), (rep, var)
+        assert np.array_equal(bufs[0][1].cpu().numpy().view(np.uint32), eager)
+    plan.close()
+
+
+def test_empty_unused_and_capacity(orc, scene):
+    import torch
+    pts, d = scene
+    plan = pcr.BatchPlan(d, capacity=3)
+    plan.launch([])
+    torch.cuda.synchronize()
+    views = make_views(2, seed=3)
+    bufs = []
+    pv = []
+    for m, W, H, var in views:
+        fb = pcr.alloc_fb(W, H, var)
+        img = torch.zeros(W * H, dtype=torch.int32, device="cuda")
+        bufs.append(img)
+        pv.append(pcr.make_view(m, W, H, var, fb, img))
+    pv[1].variant = -1          # unused slot: left untouched
+    plan.launch(pv)
+    torch.cuda.synchronize()
+    m, W, H, var = views[0]
+    _, eimg = oracle_frame(orc, pts, m, W, H, var)
+    assert np.array_equal(bufs[0].cpu().numpy().view(np.uint32), eimg)
+    assert not bufs[1].cpu().numpy().any()
+    with pytest.raises(pcr.PcrError) as e:
+        plan.launch(pv * 2)
+    assert e.value.code == pcr.EINVAL
+    plan.close()
+
+
+def test_large_views_group_split(orc):
+    """Views whose framebuffers exceed one group's cache budget are split over
+    several point passes; 1080p and 4K views of a 2M-point terrain."""
+    import torch
+    pts = synth.terrain(2_000_000, seed=2)
+    d = upload(pts)
+    views = [(synth.terrain_oblique(1920, 1080), 1920, 1080, pcr.DEDUP),
+             (synth.terrain_oblique(3840, 2160), 3840, 2160, pcr.HQ),
+             (synth.terrain_closeup(3840, 2160), 3840, 2160, pcr.BASIC),
+             (synth.terrain_overview(1280, 720), 1280, 720, pcr.HQ)]
+    plan = pcr.BatchPlan(d, capacity=4)
+    bufs = run_batch(plan, views)
+    for (m, W, H, var), (fb, img) in zip(views, bufs):
+        _, eimg = oracle_frame(orc, pts, m, W, H, var)
+        assert np.array_equal(img.cpu().numpy().view(np.uint32), eimg)
+    plan.close()
+    torch.cuda.synchronize()
