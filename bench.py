@@ -195,6 +195,307 @@ def leg_main(args):
     return rec
 
 
+def upload_reordered(pts, order=None, seed=3):
+    """Host cloud -> device, optionally reordered on the GPU (one-time step)."""
+    import torch
+    from paper_2104_07526_amd import pcr
+    d = to_device(pts)
+    if order is None:
+        return d, 0.0
+    n = len(pts)
+    scratch = torch.empty(pcr.reorder_scratch_bytes(n, order, 128), dtype=torch.uint8, device="cuda")
+    out = torch.empty_like(d)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    pcr.reorder(d, order, 128, seed, out=out, want_perm=False, scratch=scratch)
+    e1.record()
+    torch.cuda.synchronize()
+    del scratch, d
+    return out, e0.elapsed_time(e1)
+
+
+def time_frames(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def leg_hq(args):
+    """300M-point building scene, shuffled Morton, high-quality blend at
+    2560x1440 (depth pass + colour pass + resolve), against the closest-point
+    variants on the same frame."""
+    import torch
+    from paper_2104_07526_amd import pcr, synth
+    n, W, H = 300_000_000, 2560, 1440
+    t0 = time.perf_counter()
+    pts = synth.buildings(n, seed=4)
+    log(f"generated {n} building points in {time.perf_counter() - t0:.1f} s")
+    m = synth.buildings_overview(W, H, seed=4)
+    d, rms = upload_reordered(pts, pcr.ORDER_MORTON_SHUFFLE)
+    del pts
+    img = torch.empty(W * H, dtype=torch.int32, device="cuda")
+    out = {}
+    for name, var in (("hq", pcr.HQ), ("hq_plain", pcr.HQ | pcr.F_PLAIN), ("dedup", pcr.DEDUP),
+                      ("basic", pcr.BASIC)):
+        fb = pcr.alloc_fb(W, H, var)
+
+        def frame():
+            pcr.fb_clear(fb, W, H, var)
+            pcr.render(d, m, W, H, var, fb)
+            pcr.resolve(fb, W, H, var, out=img)
+        ms = time_frames(frame, args.steps, args.warmup)
+        bpp = 32 if (var & 0xFF) == pcr.HQ else 16
+        out[name] = {"frame_ms": round(ms, 4), "Gpts_s": round(n / ms / 1e6, 2),
+                     "GB_s": round(bpp * n / ms / 1e6, 1), "hbm_frac": round(bpp * n / ms / 1e6 / HBM_PEAK_GBS, 4)}
+        del fb
+    return {"metric": METRIC, "value": out["hq"]["Gpts_s"], "unit": "Gpts/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": out["hq"]["frame_ms"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+u64",
+            "data": "synthetic",
+            "config": {"workload": "buildings 300M points, shuffled Morton (batches of 128), 2560x1440, "
+                                   "high-quality blend (epsilon 1%), frame = clear + 2 passes + resolve",
+                       "points": n, "resolution": [W, H]},
+            "detail": {"variants": out, "reorder_ms": round(rms, 2)}}
+
+
+def leg_big(args):
+    """The 796M-point cloud (12.7 GB), shuffled Morton, 1920x1080: basic,
+    dedup and HQ frames."""
+    import torch
+    from paper_2104_07526_amd import pcr, synth
+    n, W, H = 796_000_000, 1920, 1080
+    t0 = time.perf_counter()
+    pts = synth.buildings(n, seed=4)
+    log(f"generated {n} building points in {time.perf_counter() - t0:.1f} s")
+    m = synth.buildings_overview(W, H, seed=4)
+    d, rms = upload_reordered(pts, pcr.ORDER_MORTON_SHUFFLE)
+    del pts
+    img = torch.empty(W * H, dtype=torch.int32, device="cuda")
+    out = {}
+    for name, var in (("dedup", pcr.DEDUP), ("basic", pcr.BASIC), ("hq", pcr.HQ)):
+        fb = pcr.alloc_fb(W, H, var)
+        timer = Timer()
+
+        def frame():
+            pcr.fb_clear(fb, W, H, var)
+            timer.start(name)
+            pcr.render(d, m, W, H, var, fb)
+            timer.stop(name)
+            pcr.resolve(fb, W, H, var, out=img)
+        ms = time_frames(frame, args.steps, args.warmup)
+        kms = float(np.median(timer.ms(name)[args.warmup:]))
+        bpp = 32 if (var & 0xFF) == pcr.HQ else 16
+        out[name] = {"frame_ms": round(ms, 4), "render_ms": round(kms, 4), "Gpts_s": round(n / ms / 1e6, 2),
+                     "GB_s": round(bpp * n / ms / 1e6, 1),
+                     "render_hbm_frac": round(bpp * n / kms / 1e6 / HBM_PEAK_GBS, 4)}
+        del fb
+    return {"metric": METRIC, "value": out["dedup"]["Gpts_s"], "unit": "Gpts/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": out["dedup"]["frame_ms"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+u64",
+            "data": "synthetic",
+            "config": {"workload": "buildings 796M points (12.7 GB), shuffled Morton, 1920x1080 overview; "
+                                   "dedup (value), basic and HQ frames", "points": n, "resolution": [W, H]},
+            "detail": {"variants": out, "reorder_ms": round(rms, 2),
+                       "paper_context": "RTX 3090, 796M-point scan: 15.26 ms (dedup, Morton), 17.84 ms "
+                                        "(atomicMin, shuffled Morton)"}}
+
+
+RES_CYCLE = [(1280, 720), (1920, 1080), (3840, 2160)]
+
+
+def batch_views(count, seed=5):
+    from paper_2104_07526_amd import pcr, synth
+    views = []
+    for i, (eye, tgt, up) in enumerate(synth.random_poses(count, seed=seed)):
+        W, H = RES_CYCLE[i % 3]
+        views.append((synth.mvp(eye, tgt, up, W, H), W, H, pcr.BASIC if i % 2 == 0 else pcr.HQ))
+    return views
+
+
+def leg_batch(args):
+    """64 camera views of one 145M-point cloud (100M terrain + 45M buildings,
+    shuffled Morton), framebuffers 1280x720 / 1920x1080 / 3840x2160, basic and
+    HQ alternating: one autotuned batch plan (single hipGraph replay) against
+    64 single-view renders in sequence; outputs compared for identity."""
+    import torch
+    from paper_2104_07526_amd import pcr, synth, tune
+    nt, nb = 100_000_000, 45_000_000
+    n = nt + nb
+    t0 = time.perf_counter()
+    pts = synth.terrain_and_buildings(nt, nb, seed=5)
+    log(f"generated {n} points in {time.perf_counter() - t0:.1f} s")
+    d, rms = upload_reordered(pts, pcr.ORDER_MORTON_SHUFFLE)
+    del pts
+    views = batch_views(64)
+    fbs = [pcr.alloc_fb(W, H, var) for _, W, H, var in views]
+    imgs = [torch.empty(W * H, dtype=torch.int32, device="cuda") for _, W, H, _ in views]
+    ref = [torch.empty_like(i) for i in imgs]
+
+    def sequential(best):
+        for (m, W, H, var), fb, im in zip(views, fbs, ref):
+            v = pcr.DEDUP if (best and var == pcr.BASIC) else var
+            pcr.fb_clear(fb, W, H, v)
+            pcr.render(d, m, W, H, v, fb)
+            pcr.resolve(fb, W, H, v, out=im)
+    log("batch leg: sequential single-view renders")
+    seq_best = time_frames(lambda: sequential(True), max(1, args.steps // 2), 1)
+    seq_plain = time_frames(lambda: sequential(False), 1, 0)
+    log("batch leg: autotuning the plan")
+    pviews = [pcr.make_view(m, W, H, var, fb, im) for (m, W, H, var), fb, im in zip(views, fbs, imgs)]
+    best_tune, table = tune.tune_batch(d, pviews, reps=2)
+    log(f"batch leg: timing the tuned plan {best_tune}")
+    plan = pcr.BatchPlan(d, len(pviews), tune=best_tune)
+    bms = time_frames(lambda: plan.launch(pviews), args.steps, args.warmup)
+    torch.cuda.synchronize()
+    sequential(True)
+    torch.cuda.synchronize()
+    plan.launch(pviews)
+    torch.cuda.synchronize()
+    same = all(torch.equal(a, b) for a, b in zip(imgs, ref))
+    plan.close()
+    pv = n * len(views)
+    return {"metric": METRIC, "value": round(pv / bms / 1e6, 2), "unit": "Gpts/s (point-views)", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(bms, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32+u64", "data": "synthetic",
+            "config": {"workload": "145M points (terrain 100M + buildings 45M), shuffled Morton; 64 views, "
+                                   "1280x720/1920x1080/3840x2160 cycling, basic/HQ alternating; one batch "
+                                   "= clear + render + resolve of all 64 views", "points": n, "views": 64},
+            "detail": {"batched_ms": round(bms, 3), "sequential_best_ms": round(seq_best, 3),
+                       "sequential_plain_ms": round(seq_plain, 3),
+                       "speedup_vs_sequential_best": round(seq_best / bms, 3),
+                       "speedup_vs_sequential_plain": round(seq_plain / bms, 3),
+                       "identical_images": bool(same), "tune": best_tune, "tune_table": table[:8],
+                       "reorder_ms": round(rms, 2)}}
+
+
+def leg_serve(args):
+    """Eight resident clouds (10M-796M points, 36.8 GB), Poisson request load
+    at fractions of the one-at-a-time service rate; continuous-batching server
+    against a one-at-a-time server on the same arrival sequence."""
+    import threading
+
+    import torch
+    from paper_2104_07526_amd import pcr, synth
+    from paper_2104_07526_amd.serve import GpuBackend, Request, Server, percentile
+    sizes = [10_000_000, 50_000_000, 100_000_000, 145_000_000, 300_000_000, 400_000_000, 500_000_000,
+             796_000_000]
+    if args.n < 100_000_000:                         # reduced sizes for a quick run
+        sizes = [max(1_000_000, s * args.n // 100_000_000) for s in sizes]
+    clouds = []
+    t0 = time.perf_counter()
+    for i, sz in enumerate(sizes):
+        gen = synth.terrain if i % 2 == 0 else synth.buildings
+        pts = gen(sz, seed=10 + i)
+        d, _ = upload_reordered(pts, pcr.ORDER_MORTON_SHUFFLE, seed=6)
+        del pts
+        clouds.append(d)
+        log(f"cloud {i}: {sz} points resident ({time.perf_counter() - t0:.0f} s)")
+    res = [(1280, 720), (1920, 1080), (2560, 1440), (3840, 2160)]
+    rng = np.random.default_rng(6)
+
+    def make_requests(k):
+        reqs = []
+        poses = synth.random_poses(k, seed=int(rng.integers(1 << 30)))
+        for (eye, tgt, up) in poses:
+            c = int(rng.integers(0, len(clouds)))
+            W, H = res[int(rng.integers(0, 4))]
+            var = pcr.HQ if rng.random() < 0.3 else pcr.BASIC
+            reqs.append(Request(c, synth.mvp(eye, tgt, up, W, H), W, H, var))
+        return reqs
+    budget = 2 << 30
+    # One-at-a-time service: clear + render + resolve of one request, waited
+    # for; basic requests use the deduplicating single-view path.
+    fb = torch.empty(budget, dtype=torch.uint8, device="cuda")
+    img = torch.empty(3840 * 2160, dtype=torch.int32, device="cuda")
+
+    def plain(r, out=None):
+        v = pcr.DEDUP if r.variant == pcr.BASIC else r.variant
+        pcr.fb_clear(fb, r.w, r.h, v)
+        pcr.render(clouds[r.cloud], r.mvp, r.w, r.h, v, fb)
+        pcr.resolve(fb, r.w, r.h, v, out=img if out is None else out)
+        torch.cuda.synchronize()
+    cal = make_requests(200)
+    for r in cal[:20]:
+        plain(r)
+    t = time.perf_counter()
+    for r in cal:
+        plain(r)
+    svc = (time.perf_counter() - t) / len(cal)
+    mu = 1.0 / svc
+    nreq = args.requests
+    be = GpuBackend(clouds, budget_bytes=budget, capacity=16)
+    rates = {}
+    for frac in (0.5, 0.8, 1.0, 1.25):
+        lam = frac * mu
+        reqs = make_requests(nreq)
+        gaps = rng.exponential(1.0 / lam, nreq)
+        # one-at-a-time server on this arrival sequence
+        start = time.perf_counter() + 0.05
+        arr = start + np.cumsum(gaps)
+        lat_p = []
+        for r, a in zip(reqs, arr):
+            while time.perf_counter() < a:
+                pass
+            plain(r)
+            lat_p.append(time.perf_counter() - a)
+        wall_p = time.perf_counter() - start
+        # continuous-batching server on the same sequence, driven inline by
+        # the arrival loop (no second Python thread competing for the GIL)
+        srv = Server(be, budget_bytes=budget)
+        start = time.perf_counter() + 0.05
+        arr = start + np.cumsum(gaps)
+        futs = []
+        i = 0
+        busy = True
+        while i < nreq or busy:
+            now = time.perf_counter()
+            while i < nreq and arr[i] <= now:
+                reqs[i].arrival = float(arr[i])
+                futs.append(srv.submit(reqs[i]))
+                i += 1
+            busy = srv.step()
+        out = [f.result(timeout=600) for f in futs]
+        wall_b = max(o.finished for o in out) - start
+        lat_b = [o.latency for o in out]
+        pts_total = sum(pcr._npoints(clouds[r.cloud]) for r in reqs)
+        rates[f"{frac:.2f}"] = {
+            "lambda_req_s": round(lam, 1),
+            "plain": {"p50_ms": round(1e3 * percentile(lat_p, 50), 3), "p99_ms": round(1e3 * percentile(lat_p, 99), 3),
+                      "Gpts_s": round(pts_total / wall_p / 1e9, 2)},
+            "batched": {"p50_ms": round(1e3 * percentile(lat_b, 50), 3), "p99_ms": round(1e3 * percentile(lat_b, 99), 3),
+                        "Gpts_s": round(pts_total / wall_b / 1e9, 2),
+                        "mean_batch": round(float(np.mean([o.batch_size for o in out])), 2),
+                        "failed": sum(o.status != "ok" for o in out)},
+        }
+        log(f"rate {frac}: {rates[f'{frac:.2f}']}")
+        # identity: a sample of results against the one-at-a-time render
+        chk = torch.empty(3840 * 2160, dtype=torch.int32, device="cuda")
+        same = True
+        for r, o in list(zip(reqs, out))[:: max(1, nreq // 20)]:
+            plain(r, out=chk)
+            same &= bool(torch.equal(o.image, chk[: r.w * r.h]))
+        rates[f"{frac:.2f}"]["identical_sample"] = same
+    be.close()
+    top = rates["1.00"]
+    return {"metric": METRIC, "value": top["batched"]["Gpts_s"], "unit": "Gpts/s", "n_gpus": 1,
+            "steps": nreq, "warmup": 20, "ms_per_step": round(1e3 / mu, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32+u64", "data": "synthetic",
+            "config": {"workload": "8 resident clouds " + "/".join(f"{s // 1_000_000}M" for s in sizes) +
+                                   "; Poisson arrivals at 0.5/0.8/1.0/1.25 x one-at-a-time rate; requests: "
+                                   "random cloud, pose, 720p-4K, basic/HQ 70/30; 2 GB framebuffer budget",
+                       "requests_per_rate": nreq},
+            "detail": {"service_ms_one_at_a_time": round(1e3 * svc, 3), "rates": rates,
+                       "p50_ms_at_1.0": top["batched"]["p50_ms"], "p99_ms_at_1.0": top["batched"]["p99_ms"]}}
+
+
 def leg_calib(args):
     """A plain device-to-device copy of 1 GiB: reference for FETCH_SIZE and
     WRITE_SIZE counters."""
@@ -223,6 +524,7 @@ def main():
     ap.add_argument("--n", type=int, default=100_000_000)
     ap.add_argument("--leg", default="main", choices=["main", "hq", "big", "batch", "serve", "calib"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--requests", type=int, default=600, help="requests per arrival rate (serve leg)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the renderer runs on a single MI355X here "
@@ -233,7 +535,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     ensure_built()
-    legs = {"main": leg_main, "calib": leg_calib}
+    legs = {"main": leg_main, "calib": leg_calib, "hq": leg_hq, "big": leg_big, "batch": leg_batch,
+            "serve": leg_serve}
     if args.leg not in legs:
         print(f"leg {args.leg} is not available", file=sys.stderr)
         sys.exit(1)

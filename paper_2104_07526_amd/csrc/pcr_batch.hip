@@ -183,15 +183,26 @@ __device__ __forceinline__ void lmin64(u64 *p, u64 v) {
     if (v < cur) __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// PASS = 0: closest-point views (64-bit keys) and HQ depth (32-bit depth);
+// One LDS table serves all views of a group: its tag packs the view's slot in
+// the group (5 bits) above the pixel index (27 bits).  A tile is projected into
+// every view of its group in turn; the table is flushed to the framebuffers
+// only when it is half full and at the end of the tile.
+constexpr uint32_t kPidBits = 27;
+constexpr uint32_t kPidMask = (1u << kPidBits) - 1u;
+constexpr uint32_t kMaxGroup = 32;
+
+// PASS = 0: closest-point views (64-bit keys) and HQ depth (depth bits);
 // PASS = 1: HQ colour sums.
 template <int PPT, int PASS>
 __global__ __launch_bounds__(kBatchWg) void k_batch_pass(const u32x4 *__restrict__ pts, uint64_t n,
                                                          unsigned char *base, TableLayout L, uint32_t hbits) {
     extern __shared__ __align__(16) unsigned char smem[];
+    // The group's views, staged once per item: camera and viewport, buffers.
+    __shared__ View vpar[kMaxGroup];
+    __shared__ u64 vbuf[kMaxGroup][2];  // per group slot: fb (or D) and S
+    __shared__ uint32_t vhq[kMaxGroup];
     BLds S(smem, hbits);
     Table t = table(base, L);
-    Header *hdr = (Header *)base;
     const uint32_t HS = 1u << hbits;
     const uint32_t T = kBatchWg * PPT;
     const uint64_t ntiles = (n + T - 1) / T;
@@ -202,12 +213,44 @@ __global__ __launch_bounds__(kBatchWg) void k_batch_pass(const u32x4 *__restrict
         S.val[2 * s + 1] = 0ull;
     }
     if (threadIdx.x == 0) *S.count = 0;
-    for (;;) {
+    bar_lds();
+
+    // Writes the table's entries to their views' buffers and empties it.
+    auto flush = [&]() {
         bar_lds();
-        if (threadIdx.x == 0) *S.item = atomicAdd(&hdr->counter[PASS], 1u);
+        const uint32_t cnt = *S.count;
         bar_lds();
-        const uint64_t item = *S.item;
-        if (item >= total) break;  // every workgroup reaches this exit
+        if (threadIdx.x == 0) *S.count = 0;
+        for (uint32_t k = threadIdx.x; k < cnt; k += kBatchWg) {
+            uint32_t h = S.list[k];
+            uint32_t tag = S.tag[h];
+            uint32_t vs = tag >> kPidBits, pid = tag & kPidMask;
+            u64 a = S.val[2 * h], b = S.val[2 * h + 1];
+            S.tag[h] = kEmptyPid;
+            S.val[2 * h] = PASS ? 0ull : kEmptyKey;
+            S.val[2 * h + 1] = 0ull;
+            if (PASS == 0) {
+                if (vhq[vs]) {
+                    uint32_t *D = (uint32_t *)vbuf[vs][0];
+                    if ((uint32_t)a < D[pid]) gmin_u32(D + pid, (uint32_t)a);
+                } else {
+                    gmin_u64((u64 *)vbuf[vs][0] + pid, a);
+                }
+            } else {
+                u64 *Sm = (u64 *)vbuf[vs][1];
+                gadd_u64(Sm + 2 * (u64)pid, a);
+                gadd_u64(Sm + 2 * (u64)pid + 1, b);
+            }
+        }
+        bar_lds();
+    };
+
+    // Static schedule: workgroup b takes items b, b + G, b + 2G, ... in
+    // group-major order (no shared queue: same-address atomics serialise at
+    // the memory-side atomic unit).  The group's views are restaged only when
+    // the group changes.
+    uint32_t cur_g = 0xFFFFFFFFu, gcount = 0;
+    for (uint64_t item = blockIdx.x; item < total; item += gridDim.x) {
         const uint32_t g = (uint32_t)(item / ntiles);
         const uint64_t tile = item - (uint64_t)g * ntiles;
         const uint64_t first = tile * T;
@@ -218,67 +261,79 @@ __global__ __launch_bounds__(kBatchWg) void k_batch_pass(const u32x4 *__restrict
             uint32_t k = (uint32_t)(j * kBatchWg + threadIdx.x);
             p[j] = load_point(pts + first + (k < rem ? k : (uint32_t)(rem - 1)));
         }
-        const Group grp = t.groups[PASS][g];
-        for (uint32_t vi = 0; vi < grp.count; ++vi) {
-            const DevView &dv = t.views[t.index[PASS][grp.first + vi]];
-            const View v = dv.v;
-            const bool hq = dv.variant == PCR_HQ;
+        if (g != cur_g) {
+            const Group grp = t.groups[PASS][g];
+            gcount = (uint32_t)__builtin_amdgcn_readfirstlane((int)grp.count);
+            if (threadIdx.x < gcount) {
+                const DevView &dv = t.views[t.index[PASS][grp.first + threadIdx.x]];
+                vpar[threadIdx.x] = dv.v;
+                vhq[threadIdx.x] = dv.variant == PCR_HQ;
+                vbuf[threadIdx.x][0] = (u64)(dv.variant == PCR_HQ ? (void *)dv.D : (void *)dv.fb);
+                vbuf[threadIdx.x][1] = (u64)dv.S;
+            }
+            cur_g = g;
+            bar_lds();
+        }
+        for (uint32_t vs = 0; vs < gcount; ++vs) {
+            const View v = vpar[vs];
+            const bool hq = vhq[vs] != 0;
+            u64 *const fbv = (u64 *)vbuf[vs][0];
+            uint32_t *const Dv = (uint32_t *)vbuf[vs][0];
+            u64 *const Sv = (u64 *)vbuf[vs][1];
+            uint32_t pids[PPT], dbs[PPT];
 #pragma unroll
-            for (int j = 0; j < PPT; ++j) {
-                uint32_t dbits;
-                uint32_t pid = project(v, __uint_as_float(p[j].x), __uint_as_float(p[j].y),
-                                       __uint_as_float(p[j].z), dbits);
-                if ((uint64_t)(j * kBatchWg + threadIdx.x) >= rem) pid = kEmptyPid;
-                if (pid == kEmptyPid) continue;
-                if (PASS == 0) {
-                    u64 val = hq ? (u64)dbits : make_key(dbits, p[j].w);
-                    uint32_t h = S.slot(pid);
+            for (int j = 0; j < PPT; ++j)
+                pids[j] = project_wave(v, p[j], (uint64_t)(j * kBatchWg + threadIdx.x) < rem, dbs[j]);
+            if (PASS == 0) {
+#pragma unroll
+                for (int j = 0; j < PPT; ++j) {
+                    const uint32_t pid = pids[j];
+                    if (pid == kEmptyPid) continue;
+                    const uint32_t key = (vs << kPidBits) | pid;
+                    u64 val = hq ? (u64)dbs[j] : make_key(dbs[j], p[j].w);
+                    uint32_t h = S.slot(key);
                     if (h != 0xFFFFFFFFu) {
                         lmin64(S.val + 2 * h, val);
                     } else if (hq) {
-                        gmin_u32(dv.D + pid, dbits);
+                        gmin_u32(Dv + pid, dbs[j]);
                     } else {
-                        gmin_u64(dv.fb + pid, val);
+                        gmin_u64(fbv + pid, val);
                     }
-                } else {
-                    float limit = __uint_as_float(dv.D[pid]) * 1.01f;
-                    if (!(__uint_as_float(dbits) <= limit)) continue;
+                }
+            } else {
+                // All closest-depth reads of the tile back to back, then the sums.
+                uint32_t dref[PPT];
+#pragma unroll
+                for (int j = 0; j < PPT; ++j) dref[j] = Dv[pids[j] != kEmptyPid ? pids[j] : 0u];
+#pragma unroll
+                for (int j = 0; j < PPT; ++j) {
+                    const uint32_t pid = pids[j];
+                    if (pid == kEmptyPid) continue;
+                    if (!(__uint_as_float(dbs[j]) <= __uint_as_float(dref[j]) * 1.01f)) continue;
+                    const uint32_t key = (vs << kPidBits) | pid;
                     u64 r = p[j].w & 0xFFu, gg = (p[j].w >> 8) & 0xFFu, bl = (p[j].w >> 16) & 0xFFu;
                     u64 rg = (r << 32) | gg, ba = (bl << 32) | 1u;
-                    uint32_t h = S.slot(pid);
+                    uint32_t h = S.slot(key);
                     if (h != 0xFFFFFFFFu) {
                         __hip_atomic_fetch_add(S.val + 2 * h, rg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                         __hip_atomic_fetch_add(S.val + 2 * h + 1, ba, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     } else {
-                        gadd_u64(dv.S + 2 * (u64)pid, rg);
-                        gadd_u64(dv.S + 2 * (u64)pid + 1, ba);
+                        gadd_u64(Sv + 2 * (u64)pid, rg);
+                        gadd_u64(Sv + 2 * (u64)pid + 1, ba);
                     }
                 }
             }
-            bar_lds();
-            const uint32_t cnt = *S.count;
-            bar_lds();
-            if (threadIdx.x == 0) *S.count = 0;
-            for (uint32_t k = threadIdx.x; k < cnt; k += kBatchWg) {
-                uint32_t h = S.list[k];
-                uint32_t pid = S.tag[h];
-                u64 a = S.val[2 * h], b = S.val[2 * h + 1];
-                S.tag[h] = kEmptyPid;
-                S.val[2 * h] = PASS ? 0ull : kEmptyKey;
-                S.val[2 * h + 1] = 0ull;
-                if (PASS == 0) {
-                    if (hq) {
-                        if ((uint32_t)a < dv.D[pid]) gmin_u32(dv.D + pid, (uint32_t)a);
-                    } else {
-                        gmin_u64(dv.fb + pid, a);
-                    }
-                } else {
-                    gadd_u64(dv.S + 2 * (u64)pid, a);
-                    gadd_u64(dv.S + 2 * (u64)pid + 1, b);
-                }
+            // Flush early when the table is half full.  The decision must be
+            // the same in every wave: all waves read the count between two
+            // barriers, so none inserts again before all have read it.
+            if (vs + 1 < gcount) {
+                bar_lds();
+                const uint32_t fill = (uint32_t)__builtin_amdgcn_readfirstlane((int)*S.count);
+                bar_lds();
+                if (fill > HS / 2) flush();
             }
-            bar_lds();
         }
+        flush();
     }
 }
 
@@ -460,6 +515,8 @@ extern "C" int pcr_batch_launch(pcr_batch *b, const pcr_view *views, uint32_t nv
         int rc = check_image(v.w, v.h);
         if (rc == PCR_OK) rc = check_variant(v.variant & 0xFF);
         if (rc != PCR_OK) return rc;
+        if ((uint64_t)v.w * v.h > kPidMask)
+            return fail(PCR_EINVAL, "view %u: batched views hold at most 2^27 - 1 pixels", i);
         if (!v.fb || ((uintptr_t)v.fb & 15) || !v.rgba_out || ((uintptr_t)v.rgba_out & 3))
             return fail(PCR_EINVAL, "view %u: framebuffer must be 16-byte aligned, rgba_out 4-byte aligned", i);
         DevView d{};
@@ -480,7 +537,7 @@ extern "C" int pcr_batch_launch(pcr_batch *b, const pcr_view *views, uint32_t nv
     memset(h, 0, sizeof(Header));
     h->nviews = (uint32_t)dv.size();
     memcpy(st + B.lay.views, dv.data(), dv.size() * sizeof(DevView));
-    const uint32_t maxg = B.sh.group ? B.sh.group : 16;
+    const uint32_t maxg = std::min<uint32_t>(B.sh.group ? B.sh.group : 16, kMaxGroup);
     for (int pass = 0; pass < 2; ++pass) {
         Group *gs = (Group *)(st + B.lay.groups[pass]);
         uint32_t *ix = (uint32_t *)(st + B.lay.index[pass]);

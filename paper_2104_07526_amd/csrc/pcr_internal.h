@@ -47,21 +47,54 @@ inline View make_view(const float *mvp, uint32_t W, uint32_t H) {
 
 // Projection (Sec. 3.1): clip = M * (x, y, z, 1); cull unless w > 0; one
 // correctly rounded reciprocal; half-open viewport test in float; truncation.
-// Returns the pixel index, or kEmptyPid when the point is culled, and the
-// depth bits (the linear w) in dbits.
-__device__ __forceinline__ uint32_t project(const View &v, float x, float y, float z,
-                                            uint32_t &dbits) {
-    float cx = ((v.m[0] * x + v.m[1] * y) + v.m[2] * z) + v.m[3];
-    float cy = ((v.m[4] * x + v.m[5] * y) + v.m[6] * z) + v.m[7];
-    float cw = ((v.m[12] * x + v.m[13] * y) + v.m[14] * z) + v.m[15];
-    float rw = 1.0f / cw;
-    float fx = (cx * rw + 1.0f) * v.hw;
-    float fy = (cy * rw + 1.0f) * v.hh;
-    bool ok = (cw > 0.0f) && (fx >= 0.0f) && (fx < v.fW) && (fy >= 0.0f) && (fy < v.fH);
-    dbits = __float_as_uint(cw);
+// Split in two so that a whole wavefront of surely culled points can skip the
+// division: clip() computes the clip coordinates, finish() the pixel index
+// (kEmptyPid when culled) and the depth bits (the linear w) from them.
+struct Clip {
+    float cx, cy, cw;
+};
+
+__device__ __forceinline__ Clip clip(const View &v, float x, float y, float z) {
+    Clip c;
+    c.cx = ((v.m[0] * x + v.m[1] * y) + v.m[2] * z) + v.m[3];
+    c.cy = ((v.m[4] * x + v.m[5] * y) + v.m[6] * z) + v.m[7];
+    c.cw = ((v.m[12] * x + v.m[13] * y) + v.m[14] * z) + v.m[15];
+    return c;
+}
+
+// True only for points that finish() culls for certain: behind the camera, or
+// more than 0.1% outside the view cone in clip space (the rounding of the
+// exact path is below 1e-6 relative).  NaN compares false: not certain.
+__device__ __forceinline__ bool surely_culled(const Clip &c) {
+    float lim = c.cw * 1.001f;
+    return c.cw <= 0.0f || c.cx > lim || c.cx < -lim || c.cy > lim || c.cy < -lim;
+}
+
+__device__ __forceinline__ uint32_t finish(const View &v, const Clip &c, uint32_t &dbits) {
+    float rw = 1.0f / c.cw;
+    float fx = (c.cx * rw + 1.0f) * v.hw;
+    float fy = (c.cy * rw + 1.0f) * v.hh;
+    bool ok = (c.cw > 0.0f) && (fx >= 0.0f) && (fx < v.fW) && (fy >= 0.0f) && (fy < v.fH);
+    dbits = __float_as_uint(c.cw);
     uint32_t px = (uint32_t)(ok ? fx : 0.0f);
     uint32_t py = (uint32_t)(ok ? fy : 0.0f);
     return ok ? py * v.W + px : kEmptyPid;
+}
+
+__device__ __forceinline__ uint32_t project(const View &v, float x, float y, float z,
+                                            uint32_t &dbits) {
+    return finish(v, clip(v, x, y, z), dbits);
+}
+
+// Projection with the wavefront-level early out: returns kEmptyPid for every
+// lane when no lane of the wavefront can be visible (`live` false = lane past
+// the end of the buffer).  Must be called by the whole wavefront.
+__device__ __forceinline__ uint32_t project_wave(const View &v, const u32x4 &p, bool live, uint32_t &dbits) {
+    Clip c = clip(v, __uint_as_float(p.x), __uint_as_float(p.y), __uint_as_float(p.z));
+    dbits = __float_as_uint(c.cw);
+    if (__ballot(live && !surely_culled(c)) == 0) return kEmptyPid;
+    uint32_t pid = finish(v, c, dbits);
+    return live ? pid : kEmptyPid;
 }
 
 __device__ __forceinline__ u32x4 load_point(const u32x4 *p) {

@@ -39,14 +39,64 @@ int launch_fill(void *p, size_t bytes, uint32_t word, hipStream_t s) {
 // listing); otherwise neighbouring lane pairs merge (second listing).  Keys are
 // compared whole, so a lane that loses can never hold the pixel's minimum.
 // ---------------------------------------------------------------------------
-template <typename V>
-__device__ __forceinline__ V wave_min(V x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        V y = __shfl_xor(x, o, 64);
-        x = y < x ? y : x;
-    }
-    return x;
+// Wave-wide reductions with DPP moves (VALU, no LDS traffic): pairs, quads,
+// half rows and rows by quad_perm / row mirrors, then rows combined by
+// row_bcast:15 and row_bcast:31; lane 63 ends with the total.  Lanes outside
+// a DPP pattern's row mask keep the identity.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ u64 dpp64(u64 x, u64 ident) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)ident, (int)(uint32_t)x, CTRL, ROWS, 0xF, false);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(ident >> 32), (int)(uint32_t)(x >> 32), CTRL,
+                                                        ROWS, 0xF, false);
+    return ((u64)hi << 32) | lo;
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp32(uint32_t x, uint32_t ident) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)ident, (int)x, CTRL, ROWS, 0xF, false);
+}
+
+__device__ __forceinline__ u64 vmin(u64 a, u64 b) { return b < a ? b : a; }
+__device__ __forceinline__ uint32_t vmin(uint32_t a, uint32_t b) { return b < a ? b : a; }
+
+__device__ __forceinline__ u64 readlane64(u64 x, uint32_t lane) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, lane);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), lane);
+    return ((u64)hi << 32) | lo;
+}
+
+// Minimum over the wavefront (uniform result).
+__device__ __forceinline__ u64 wave_min(u64 x) {
+    const u64 I = ~0ull;
+    x = vmin(x, dpp64<0xB1, 0xF>(x, I));   // quad_perm [1,0,3,2]
+    x = vmin(x, dpp64<0x4E, 0xF>(x, I));   // quad_perm [2,3,0,1]
+    x = vmin(x, dpp64<0x141, 0xF>(x, I));  // row_half_mirror
+    x = vmin(x, dpp64<0x140, 0xF>(x, I));  // row_mirror
+    x = vmin(x, dpp64<0x142, 0xA>(x, I));  // row_bcast:15
+    x = vmin(x, dpp64<0x143, 0xC>(x, I));  // row_bcast:31
+    return readlane64(x, 63);
+}
+
+__device__ __forceinline__ uint32_t wave_min(uint32_t x) {
+    const uint32_t I = ~0u;
+    x = vmin(x, dpp32<0xB1, 0xF>(x, I));
+    x = vmin(x, dpp32<0x4E, 0xF>(x, I));
+    x = vmin(x, dpp32<0x141, 0xF>(x, I));
+    x = vmin(x, dpp32<0x140, 0xF>(x, I));
+    x = vmin(x, dpp32<0x142, 0xA>(x, I));
+    x = vmin(x, dpp32<0x143, 0xC>(x, I));
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+// Sum over the wavefront (uniform result), modulo 2^64.
+__device__ __forceinline__ u64 wave_sum(u64 x) {
+    x += dpp64<0xB1, 0xF>(x, 0ull);
+    x += dpp64<0x4E, 0xF>(x, 0ull);
+    x += dpp64<0x141, 0xF>(x, 0ull);
+    x += dpp64<0x140, 0xF>(x, 0ull);
+    x += dpp64<0x142, 0xA>(x, 0ull);
+    x += dpp64<0x143, 0xC>(x, 0ull);
+    return readlane64(x, 63);
 }
 
 template <typename V>
@@ -71,7 +121,7 @@ __device__ __forceinline__ bool wave_reduce(uint32_t pid, V val, bool live) {
 #pragma unroll 1
     for (int it = 0; it < 2 && act; ++it) {
         uint32_t leader = (uint32_t)__builtin_ctzll(act);
-        uint32_t p0 = __shfl(pid, leader, 64);
+        uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pid, leader);
         uint64_t m = __ballot(live && pid == p0);
         if (__popcll(m) < 4) break;
         bool in = (m >> lane) & 1ull;
@@ -97,16 +147,11 @@ __device__ __forceinline__ void wave_group_sums(uint32_t pid, u64 &rg, u64 &ba, 
 #pragma unroll 1
     for (int it = 0; it < 2 && act; ++it) {
         uint32_t leader = (uint32_t)__builtin_ctzll(act);
-        uint32_t p0 = __shfl(pid, leader, 64);
+        uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pid, leader);
         uint64_t m = __ballot(live && pid == p0);
         if (__popcll(m) < 4) break;
         bool in = (m >> lane) & 1ull;
-        u64 a = in ? rg : 0ull, b = in ? ba : 0ull;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            a += __shfl_xor(a, o, 64);
-            b += __shfl_xor(b, o, 64);
-        }
+        u64 a = wave_sum(in ? rg : 0ull), b = wave_sum(in ? ba : 0ull);
         if (in) {
             if (lane == leader) {
                 rg = a;
@@ -245,9 +290,7 @@ __global__ __launch_bounds__(1024) void k_basic(const u32x4 *__restrict__ pts, T
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             uint32_t dbits;
-            uint32_t pid = project(v, __uint_as_float(p[j].x), __uint_as_float(p[j].y),
-                                   __uint_as_float(p[j].z), dbits);
-            if (base + (uint64_t)j * wg >= tl.n) pid = kEmptyPid;
+            uint32_t pid = project_wave(v, p[j], base + (uint64_t)j * wg < tl.n, dbits);
             u64 key = make_key(dbits, p[j].w);
             bool w = pid != kEmptyPid;
             if (REDUCE) w = wave_reduce<u64>(pid, key, w);
@@ -292,9 +335,7 @@ __global__ __launch_bounds__(1024) void k_dedup(const u32x4 *__restrict__ pts, T
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             uint32_t dbits;
-            uint32_t pid = project(v, __uint_as_float(p[j].x), __uint_as_float(p[j].y),
-                                   __uint_as_float(p[j].z), dbits);
-            if (base + (uint64_t)j * wg >= tl.n) pid = kEmptyPid;
+            uint32_t pid = project_wave(v, p[j], base + (uint64_t)j * wg < tl.n, dbits);
             V val;
             if constexpr (sizeof(V) == 8)
                 val = make_key(dbits, p[j].w);
@@ -347,9 +388,7 @@ __global__ __launch_bounds__(1024) void k_hq_depth(const u32x4 *__restrict__ pts
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             uint32_t dbits;
-            uint32_t pid = project(v, __uint_as_float(p[j].x), __uint_as_float(p[j].y),
-                                   __uint_as_float(p[j].z), dbits);
-            if (base + (uint64_t)j * wg >= tl.n) pid = kEmptyPid;
+            uint32_t pid = project_wave(v, p[j], base + (uint64_t)j * wg < tl.n, dbits);
             bool w = pid != kEmptyPid;
             if (EARLYZ && w) w = dbits < peek_u32(D + pid);
             if (w) gmin_u32(D + pid, dbits);
@@ -358,13 +397,8 @@ __global__ __launch_bounds__(1024) void k_hq_depth(const u32x4 *__restrict__ pts
 }
 
 // HQ colour pass (Sec. 3.5): a point within 1% of its pixel's closest depth
-// adds (r << 32 | g) and (b << 32 | 1) to the pixel's two 64-bit sums.
-__device__ __forceinline__ bool hq_contributes(const uint32_t *__restrict__ D, uint32_t pid,
-                                               uint32_t dbits) {
-    float limit = __uint_as_float(D[pid]) * 1.01f;
-    return __uint_as_float(dbits) <= limit;
-}
-
+// (depth <= fl32(closest * 1.01f)) adds (r << 32 | g) and (b << 32 | 1) to the
+// pixel's two 64-bit sums.
 template <int PPT, bool LDS>
 __global__ __launch_bounds__(1024) void k_hq_color(const u32x4 *__restrict__ pts, Tiles tl, View v,
                                                    const uint32_t *__restrict__ D,
@@ -389,14 +423,17 @@ __global__ __launch_bounds__(1024) void k_hq_color(const u32x4 *__restrict__ pts
         const uint64_t base = first + threadIdx.x;
         u32x4 p[PPT];
         load_tile<PPT>(pts, first, wg, tl.n, p);
+        // Project every point first, then read all their closest depths back
+        // to back (one round trip for the tile instead of one per point).
+        uint32_t pids[PPT], dbs[PPT], dref[PPT];
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) pids[j] = project_wave(v, p[j], base + (uint64_t)j * wg < tl.n, dbs[j]);
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) dref[j] = D[pids[j] != kEmptyPid ? pids[j] : 0u];
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
-            uint32_t dbits;
-            uint32_t pid = project(v, __uint_as_float(p[j].x), __uint_as_float(p[j].y),
-                                   __uint_as_float(p[j].z), dbits);
-            if (base + (uint64_t)j * wg >= tl.n) pid = kEmptyPid;
-            bool live = pid != kEmptyPid;
-            if (live) live = hq_contributes(D, pid, dbits);
+            const uint32_t pid = pids[j];
+            bool live = pid != kEmptyPid && __uint_as_float(dbs[j]) <= __uint_as_float(dref[j]) * 1.01f;
             u64 r = p[j].w & 0xFFu, g = (p[j].w >> 8) & 0xFFu, bl = (p[j].w >> 16) & 0xFFu;
             u64 rg = (r << 32) | g, ba = (bl << 32) | 1u;
             wave_group_sums(pid, rg, ba, live);
@@ -653,7 +690,7 @@ extern "C" int pcr_render_ex(const pcr_point *pts, uint64_t n, const float mvp[1
     const bool chosen = (flags & kFlagMask) != 0;
     if (fam == PCR_BASIC) return render_basic(L);
     if (fam == PCR_DEDUP) {
-        if (!chosen) L.flags |= PCR_F_LDS | PCR_F_REDUCE;
+        if (!chosen) L.flags |= PCR_F_LDS;
         return render_basic(L);
     }
     // PCR_HQ: depth pass, then colour pass.

@@ -114,3 +114,25 @@ def test_large_views_group_split(orc):
         assert np.array_equal(img.cpu().numpy().view(np.uint32), eimg)
     plan.close()
     torch.cuda.synchronize()
+
+
+def test_many_views_fill_the_shared_table(orc):
+    """Sixteen views per group over a dense terrain with small tables (256 LDS
+    slots): the shared (view, pixel) table fills past half during a tile and
+    is flushed between views many times; every view still equals the oracle."""
+    import torch
+    pts = synth.terrain(1_500_000, seed=2)
+    d = upload(pts)
+    views = []
+    for i, (eye, tgt, up) in enumerate(synth.random_poses(16, seed=77)):
+        W, H = [(320, 180), (256, 256)][i % 2]
+        views.append((synth.mvp(eye, tgt, up, W, H), W, H, [pcr.BASIC, pcr.HQ][i % 2]))
+    for tune in ({"ppt": 4, "group": 16, "slots": 256}, {"ppt": 8, "group": 16, "slots": 256}):
+        plan = pcr.BatchPlan(d, capacity=16, tune=tune)
+        for _ in range(2):
+            bufs = run_batch(plan, views)
+            for (m, W, H, var), (fb, img) in zip(views, bufs):
+                _, eimg = oracle_frame(orc, pts, m, W, H, var)
+                assert np.array_equal(img.cpu().numpy().view(np.uint32), eimg)
+        plan.close()
+    torch.cuda.synchronize()

@@ -33,26 +33,37 @@ def mixed_requests(k, seed):
 
 
 def test_results_equal_solo_under_load(orc, clouds):
+    """A burst (every request admitted before the loop runs, so batches hold
+    several views) followed by a trickle served by the threaded loop while
+    earlier batches are still on the device."""
     import torch
     host, dev = clouds
     be = GpuBackend(dev, budget_bytes=8 << 20, capacity=6)
     srv = Server(be, budget_bytes=8 << 20)
+    burst = mixed_requests(24, seed=21)
+    futs = [srv.submit(r) for r in burst]
+    srv.drain()
+    sizes = [f.result().batch_size for f in futs]
+    assert max(sizes) > 1, f"no batching in the burst: {sizes}"
+    trickle = mixed_requests(40, seed=22)
     srv.start()
-    reqs = mixed_requests(60, seed=21)
-    futs = []
-    for r in reqs:
+    for r in trickle:
         futs.append(srv.submit(r))
         time.sleep(0.0002)
     res = [f.result(timeout=60) for f in futs]
     srv.stop()
     torch.cuda.synchronize()
-    assert max(r.batch_size for r in res) > 1, "no batching happened"
+    reqs = burst + trickle
+    bad = []
     for r, out in zip(reqs, res):
-        assert out.status == "ok"
+        assert out.status == "ok", (out.status, out.error)
         _, alone = render_frame(dev[r.cloud], r.mvp, r.w, r.h, r.variant)
-        assert np.array_equal(out.image.cpu().numpy().view(np.uint32), alone), r
+        got = out.image.cpu().numpy().view(np.uint32)
+        if not np.array_equal(got, alone):
+            bad.append((r.rid, r.cloud, r.w, r.h, r.variant, out.batch_size, int((got != alone).sum())))
+    assert not bad, f"served images differ from solo renders: {bad[:10]}"
     for r, out in list(zip(reqs, res))[:8]:
         _, eimg = oracle_frame(orc, host[r.cloud], r.mvp, r.w, r.h, r.variant)
-        assert np.array_equal(out.image.cpu().numpy().view(np.uint32), eimg)
-    assert srv.arena.used == 0
+        assert np.array_equal(out.image.cpu().numpy().view(np.uint32), eimg), r.rid
+    assert srv.arena.used == 0, srv.arena.used
     be.close()
