@@ -81,9 +81,11 @@ enum { PCR_BASIC = 0, PCR_DEDUP = 1, PCR_HQ = 2 };
  *   PCR_F_EARLYZ  read the stored value first, skip the atomic when it is not
  *                 larger (Sec. 3.2; safe because values only decrease)
  *   PCR_F_REDUCE  merge same-pixel updates inside a wavefront before the
- *                 atomic: the lanes sharing a leader lane's pixel (the
- *                 all-lanes-equal case of Sec. 3.3, for up to two leaders),
- *                 then neighbouring lane pairs (Sec. 3.3)
+ *                 atomic: the lanes sharing a leader lane's pixel keep their
+ *                 minimum (the all-lanes-equal case of Sec. 3.3, for up to
+ *                 two leaders with 24 or more lanes each); without PCR_F_LDS, neighbouring lane pairs
+ *                 then merge as well (Sec. 3.3).  For PCR_HQ it applies to
+ *                 the depth pass.
  *   PCR_F_LDS     merge all equal pixels of a workgroup's tile in an LDS hash
  *                 table before the atomics (Sec. 3.4's deduplication)
  *   PCR_F_PLAIN   none of the above (for PCR_HQ: one global atomic per sum
@@ -211,6 +213,15 @@ int pcr_batch_create(pcr_batch **plan, const pcr_point *pts, uint64_t n, uint32_
 int pcr_batch_launch(pcr_batch *plan, const pcr_view *views, uint32_t nviews, void *stream);
 
 int pcr_batch_destroy(pcr_batch *plan);
+
+/* Self-check of the projection's reciprocal (see the Projection paragraph):
+ * adds to *mismatches (device, uint64, 8-byte aligned) the number of floats
+ * with bit patterns in [first_bits, last_bits] for which the reciprocal used by
+ * the render kernels differs from the IEEE quotient 1.0f / w.  Zero over
+ * [0x00000001, 0x7F7FFFFF] means the fast reciprocal is exact for every
+ * positive finite float. */
+int pcr_check_reciprocal(uint32_t first_bits, uint32_t last_bits, unsigned long long *mismatches,
+                         void *stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *pcr_last_error(void);

@@ -36,7 +36,7 @@ int check_variant(int variant) {
     uint32_t flags = (uint32_t)variant & ~0xFFu;
     if (fam != PCR_BASIC && fam != PCR_DEDUP && fam != PCR_HQ)
         return fail(PCR_EINVAL, "unknown variant %d", fam);
-    uint32_t allowed = fam == PCR_HQ ? (PCR_F_EARLYZ | PCR_F_LDS | PCR_F_PLAIN | kHqPassMask) : kFlagMask;
+    uint32_t allowed = fam == PCR_HQ ? (kFlagMask | kHqPassMask) : kFlagMask;
     if ((flags & PCR_F_PLAIN) && (flags & (PCR_F_EARLYZ | PCR_F_REDUCE | PCR_F_LDS)))
         return fail(PCR_EINVAL, "PCR_F_PLAIN excludes the other path flags");
     if (flags & ~allowed) return fail(PCR_EINVAL, "flag bits 0x%x do not apply to variant %d", flags & ~allowed, fam);
@@ -115,3 +115,28 @@ int allow_lds(const void *kernel, size_t bytes) {
 extern "C" const char *pcr_last_error(void) { return pcr::g_error.c_str(); }
 
 extern "C" const char *pcr_version(void) { return "pcr 0.1 (gfx950)"; }
+
+namespace pcr {
+// Counts the floats with bit patterns in [lo, lo + count) whose reciprocal in
+// the projection differs from the IEEE division 1.0f / w.
+__global__ __launch_bounds__(256) void k_check_recip(uint32_t lo, uint64_t count, unsigned long long *bad) {
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    unsigned long long nbad = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+        float w = __uint_as_float(lo + (uint32_t)i);
+        nbad += __float_as_uint(recip_rn(w)) != __float_as_uint(1.0f / w);
+    }
+    if (nbad) atomicAdd(bad, nbad);
+}
+}  // namespace pcr
+
+extern "C" int pcr_check_reciprocal(uint32_t first_bits, uint32_t last_bits, unsigned long long *mismatches,
+                                    void *stream) {
+    if (!mismatches || ((uintptr_t)mismatches & 7) || last_bits < first_bits)
+        return pcr::fail(PCR_EINVAL, "bad reciprocal check arguments");
+    uint64_t count = (uint64_t)last_bits - first_bits + 1;
+    hipLaunchKernelGGL(pcr::k_check_recip, dim3(8192), dim3(256), 0, (hipStream_t)stream, first_bits, count,
+                       mismatches);
+    PCR_LAUNCHED();
+    return PCR_OK;
+}

@@ -206,7 +206,6 @@ __global__ __launch_bounds__(kBatchWg) void k_batch_pass(const u32x4 *__restrict
     const uint32_t HS = 1u << hbits;
     const uint32_t T = kBatchWg * PPT;
     const uint64_t ntiles = (n + T - 1) / T;
-    const uint64_t total = ntiles * t.h->ngroups[PASS];
     for (uint32_t s = threadIdx.x; s < HS; s += kBatchWg) {
         S.tag[s] = kEmptyPid;
         S.val[2 * s] = PASS ? 0ull : kEmptyKey;
@@ -245,14 +244,27 @@ __global__ __launch_bounds__(kBatchWg) void k_batch_pass(const u32x4 *__restrict
         bar_lds();
     };
 
-    // Static schedule: workgroup b takes items b, b + G, b + 2G, ... in
-    // group-major order (no shared queue: same-address atomics serialise at
-    // the memory-side atomic unit).  The group's views are restaged only when
-    // the group changes.
+    // Static, XCD-aware schedule (no shared queue: same-address atomics
+    // serialise at the memory-side atomic unit).  Workgroups are dispatched
+    // round-robin over the 8 XCDs; the workgroups of XCD x walk the groups in
+    // order and, inside each group, the contiguous tile range
+    // [x*per, (x+1)*per), so each XCD's L2 sees one part of a spatially
+    // ordered cloud.  The group's views are restaged only when the group
+    // changes.
+    const uint32_t nx = gridDim.x < 8u ? gridDim.x : 8u;  // tile ranges (one per XCD)
+    const uint32_t xcd = blockIdx.x % nx, lane_wg = blockIdx.x / nx;
+    const uint32_t wgs_x = (gridDim.x - xcd + nx - 1u) / nx;  // workgroups on this range
+    const uint64_t per = (ntiles + nx - 1) / nx;
+    const uint64_t t_lo = xcd * per, t_hi = t_lo + per < ntiles ? t_lo + per : ntiles;
+    const uint32_t ngroups = t.h->ngroups[PASS];
     uint32_t cur_g = 0xFFFFFFFFu, gcount = 0;
-    for (uint64_t item = blockIdx.x; item < total; item += gridDim.x) {
-        const uint32_t g = (uint32_t)(item / ntiles);
-        const uint64_t tile = item - (uint64_t)g * ntiles;
+    for (uint64_t item = 0;; ++item) {
+        // item-th piece of work of this workgroup: (group, tile) in group-major order
+        const uint64_t span = t_hi > t_lo ? t_hi - t_lo : 0;
+        const uint64_t mine = span > lane_wg ? (span - lane_wg + wgs_x - 1) / wgs_x : 0;
+        if (mine == 0 || item >= mine * ngroups) break;  // every workgroup reaches this exit
+        const uint32_t g = (uint32_t)(item / mine);
+        const uint64_t tile = t_lo + lane_wg + (item - (uint64_t)g * mine) * wgs_x;
         const uint64_t first = tile * T;
         const uint64_t rem = n - first;
         u32x4 p[PPT];
@@ -361,11 +373,21 @@ struct pcr_batch {
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    uint32_t grid_pass = 0, grid_io = 0;
+    uint32_t grid_pass[2] = {0, 0}, grid_io = 0;
 };
 
 namespace pcr {
 namespace {
+
+// Workgroups of a persistent pass: as many as are resident at once on the
+// device, so that no workgroup waits for another to finish its whole share.
+int resident_grid(const void *fn, size_t sm, uint32_t &grid) {
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, (int)kBatchWg, sm);
+    if (e != hipSuccess || per_cu <= 0) return fail(PCR_EHIP, "occupancy query failed: %s", hipGetErrorString(e));
+    grid = (uint32_t)per_cu * (uint32_t)device_cus();
+    return PCR_OK;
+}
 
 int launch_pass(pcr_batch *b, int pass, hipStream_t s) {
     // pass < 0: only raise the kernels' LDS limit (done before graph capture).
@@ -374,13 +396,16 @@ int launch_pass(pcr_batch *b, int pass, hipStream_t s) {
     case P:                                                                                            \
         if (pass < 0) {                                                                                \
             int rc = allow_lds((const void *)&k_batch_pass<P, 0>, sm);                                 \
-            return rc ? rc : allow_lds((const void *)&k_batch_pass<P, 1>, sm);                         \
+            if (rc == PCR_OK) rc = allow_lds((const void *)&k_batch_pass<P, 1>, sm);                   \
+            if (rc == PCR_OK) rc = resident_grid((const void *)&k_batch_pass<P, 0>, sm, b->grid_pass[0]); \
+            if (rc == PCR_OK) rc = resident_grid((const void *)&k_batch_pass<P, 1>, sm, b->grid_pass[1]); \
+            return rc;                                                                                 \
         }                                                                                              \
         if (pass)                                                                                      \
-            hipLaunchKernelGGL((k_batch_pass<P, 1>), dim3(b->grid_pass), dim3(kBatchWg), sm, s, b->pts, b->n, \
+            hipLaunchKernelGGL((k_batch_pass<P, 1>), dim3(b->grid_pass[1]), dim3(kBatchWg), sm, s, b->pts, b->n, \
                                b->dtable, b->lay, b->hbits);                                           \
         else                                                                                           \
-            hipLaunchKernelGGL((k_batch_pass<P, 0>), dim3(b->grid_pass), dim3(kBatchWg), sm, s, b->pts, b->n, \
+            hipLaunchKernelGGL((k_batch_pass<P, 0>), dim3(b->grid_pass[0]), dim3(kBatchWg), sm, s, b->pts, b->n, \
                                b->dtable, b->lay, b->hbits);                                           \
         break;
     switch (b->sh.ppt) {
@@ -449,8 +474,6 @@ extern "C" int pcr_batch_create(pcr_batch **plan, const pcr_point *pts, uint64_t
         return fail(PCR_EINVAL, "%u LDS slots do not fit", 1u << b->hbits);
     }
     b->lay = layout(capacity);
-    // Persistent grid: enough workgroups to fill every CU several times over.
-    b->grid_pass = (uint32_t)device_cus() * 8;
     b->grid_io = (uint32_t)device_cus() * 16;
     hipError_t e = hipMalloc((void **)&b->dtable, b->lay.bytes);
     if (e != hipSuccess) {

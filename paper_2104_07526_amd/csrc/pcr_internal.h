@@ -70,8 +70,25 @@ __device__ __forceinline__ bool surely_culled(const Clip &c) {
     return c.cw <= 0.0f || c.cx > lim || c.cx < -lim || c.cy > lim || c.cy < -lim;
 }
 
+// Correctly rounded 1/w: the hardware reciprocal estimate plus one FMA
+// correction step, which equals the IEEE quotient 1.0f / w for every w in
+// [2^-125, 2^126] (every float of that range is checked against the division
+// by pcr_check_reciprocal); outside that range the full division is used.
+// For w <= 0 or NaN the value is not used (the point is culled).
+__device__ __forceinline__ float recip_rn(float w) {
+    float r = __builtin_amdgcn_rcpf(w);
+    float e = __builtin_fmaf(-w, r, 1.0f);
+    float q = __builtin_fmaf(e, r, r);
+    const bool slow = (w > 0.0f && w < 0x1p-125f) || w > 0x1p126f;
+    if (__ballot(slow) != 0) {  // uniform branch: the division only runs when a lane needs it
+        float d = 1.0f / w;
+        q = slow ? d : q;
+    }
+    return q;
+}
+
 __device__ __forceinline__ uint32_t finish(const View &v, const Clip &c, uint32_t &dbits) {
-    float rw = 1.0f / c.cw;
+    float rw = recip_rn(c.cw);
     float fx = (c.cx * rw + 1.0f) * v.hw;
     float fy = (c.cy * rw + 1.0f) * v.hh;
     bool ok = (c.cw > 0.0f) && (fx >= 0.0f) && (fx < v.fW) && (fy >= 0.0f) && (fy < v.fH);

@@ -111,11 +111,12 @@ __device__ __forceinline__ V lane_pair(V x) {
     }
 }
 
-template <typename V>
+template <typename V, bool PAIRS>
 __device__ __forceinline__ bool wave_reduce(uint32_t pid, V val, bool live) {
-    // Up to two groups: the lanes sharing the first live lane's pixel keep
-    // only their minimum (with every live lane in one group this is the
-    // all-lanes-equal case of Sec. 3.3).
+    // Leader groups: the lanes sharing the first remaining live lane's pixel
+    // keep only their minimum (with every live lane in one group this is the
+    // all-lanes-equal case of Sec. 3.3).  Up to two groups of at least 24
+    // lanes; a wavefront spread over several pixels leaves after one ballot.
     const uint32_t lane = __lane_id();
     uint64_t act = __ballot(live);
 #pragma unroll 1
@@ -123,13 +124,14 @@ __device__ __forceinline__ bool wave_reduce(uint32_t pid, V val, bool live) {
         uint32_t leader = (uint32_t)__builtin_ctzll(act);
         uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pid, leader);
         uint64_t m = __ballot(live && pid == p0);
-        if (__popcll(m) < 4) break;
+        if (__popcll(m) < 24) break;
         bool in = (m >> lane) & 1ull;
         V mv = wave_min(in ? val : (V)~(V)0);
         if (in) live = val == mv;  // equal keys may all write: harmless
         act &= ~m;
     }
-    // The remaining lanes: neighbouring pairs merge (Sec. 3.3, pairs).
+    if (!PAIRS) return live;
+    // Neighbouring lane pairs merge (Sec. 3.3, pairs).
     uint32_t ppid = lane_pair(live ? pid : kEmptyPid);
     V pval = lane_pair(val);
     bool same = live && ppid == pid;
@@ -227,6 +229,32 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Collapse of a dense wavefront before the LDS table (PCR_F_REDUCE with
+// PCR_F_LDS): when at least 24 live lanes share the first live lane's pixel
+// and that pixel has no slot in the table yet, the group keeps only its
+// minimum, so that the new slot is not claimed and lowered by 24-64 lanes one
+// after another.  A pixel that already has a slot is left to the slot's early
+// test (its value is already small).  Up to two groups.
+template <typename V>
+__device__ __forceinline__ bool dense_collapse(const Lds<V> &L, uint32_t pid, V val, bool live) {
+    const uint32_t lane = __lane_id();
+    uint64_t act = __ballot(live);
+#pragma unroll 1
+    for (int it = 0; it < 2 && act; ++it) {
+        uint32_t leader = (uint32_t)__builtin_ctzll(act);
+        uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pid, leader);
+        uint64_t m = __ballot(live && pid == p0);
+        if (__popcll(m) < 24) break;
+        act &= ~m;
+        uint32_t t0 = L.tag[(p0 * 0x9E3779B1u) >> L.shift];
+        if (t0 == p0) continue;  // slot exists: the early test filters
+        bool in = (m >> lane) & 1ull;
+        V mv = wave_min(in ? val : (V)~(V)0);
+        if (in) live = val == mv;
+    }
+    return live;
+}
+
 inline size_t lds_bytes(uint32_t hbits, size_t vbytes) {
     return 16 + ((size_t)vbytes + 8) * (1u << hbits);
 }
@@ -293,7 +321,7 @@ __global__ __launch_bounds__(1024) void k_basic(const u32x4 *__restrict__ pts, T
             uint32_t pid = project_wave(v, p[j], base + (uint64_t)j * wg < tl.n, dbits);
             u64 key = make_key(dbits, p[j].w);
             bool w = pid != kEmptyPid;
-            if (REDUCE) w = wave_reduce<u64>(pid, key, w);
+            if (REDUCE) w = wave_reduce<u64, true>(pid, key, w);
             if (EARLYZ && w) w = key < peek_u64(fb + pid);
             if (w) gmin_u64(fb + pid, key);
         }
@@ -342,7 +370,7 @@ __global__ __launch_bounds__(1024) void k_dedup(const u32x4 *__restrict__ pts, T
             else
                 val = dbits;
             bool w = pid != kEmptyPid;
-            if (REDUCE) w = wave_reduce<V>(pid, val, w);
+            if (REDUCE) w = dense_collapse<V>(L, pid, val, w);
             if (w) {
                 uint32_t h = L.slot(pid, par);
                 if (h != kNoSlot) {
@@ -585,22 +613,23 @@ struct DepthL {
     static int run(const Launch &L) {
         uint32_t grid;
         Tiles tl = make_tiles(L.n, L.sh, grid);
-        bool ez = L.flags & PCR_F_EARLYZ;
+        bool ez = L.flags & PCR_F_EARLYZ, rd = L.flags & PCR_F_REDUCE;
         uint32_t *D = (uint32_t *)L.fb;
         if (L.flags & PCR_F_LDS) {
             uint32_t T = L.sh.wg * P, hb = lds_hbits(T, L.sh.slots);
             size_t sm = lds_bytes(hb, 4);
             if (sm > max_lds())
                 return fail(PCR_EINVAL, "tile of %u points needs %zu bytes of LDS", T, sm);
-            int rc = allow_lds(ez ? (const void *)&k_dedup<uint32_t, P, true, false>
-                                  : (const void *)&k_dedup<uint32_t, P, false, false>, sm);
-            if (rc) return rc;
-            if (ez)
-                hipLaunchKernelGGL((k_dedup<uint32_t, P, true, false>), dim3(grid), dim3(L.sh.wg), sm,
-                                   L.s, L.pts, tl, L.v, D, hb);
-            else
-                hipLaunchKernelGGL((k_dedup<uint32_t, P, false, false>), dim3(grid), dim3(L.sh.wg), sm,
-                                   L.s, L.pts, tl, L.v, D, hb);
+#define PCR_DD(E, R)                                                                                    \
+    do {                                                                                                \
+        if (int rc_ = allow_lds((const void *)&k_dedup<uint32_t, P, E, R>, sm)) return rc_;             \
+        hipLaunchKernelGGL((k_dedup<uint32_t, P, E, R>), dim3(grid), dim3(L.sh.wg), sm, L.s, L.pts, tl, L.v, D, hb); \
+    } while (0)
+            if (ez && rd) PCR_DD(true, true);
+            else if (ez) PCR_DD(true, false);
+            else if (rd) PCR_DD(false, true);
+            else PCR_DD(false, false);
+#undef PCR_DD
         } else if (ez) {
             hipLaunchKernelGGL((k_hq_depth<P, true>), dim3(grid), dim3(L.sh.wg), 0, L.s, L.pts, tl, L.v, D);
         } else {
@@ -690,11 +719,11 @@ extern "C" int pcr_render_ex(const pcr_point *pts, uint64_t n, const float mvp[1
     const bool chosen = (flags & kFlagMask) != 0;
     if (fam == PCR_BASIC) return render_basic(L);
     if (fam == PCR_DEDUP) {
-        if (!chosen) L.flags |= PCR_F_LDS;
+        if (!chosen) L.flags |= PCR_F_LDS | PCR_F_REDUCE;
         return render_basic(L);
     }
     // PCR_HQ: depth pass, then colour pass.
-    if (!chosen) L.flags |= PCR_F_LDS;
+    if (!chosen) L.flags |= PCR_F_LDS | PCR_F_REDUCE;
     uint32_t pass = flags & kHqPassMask;
     if (pass == 0) pass = kHqPassMask;
     if (pass & PCR_F_HQ_DEPTH) {

@@ -66,6 +66,7 @@ def _declare(lib):
         "pcr_batch_create": (I32, [P, P, U64, U32, P, P]),
         "pcr_batch_launch": (I32, [P, P, U32, P]),
         "pcr_batch_destroy": (I32, [P]),
+        "pcr_check_reciprocal": (I32, [U32, U32, P, P]),
         "pcr_last_error": (ctypes.c_char_p, []),
         "pcr_version": (ctypes.c_char_p, []),
     }
@@ -130,6 +131,15 @@ def _tune(t):
 
 def version() -> str:
     return lib().pcr_version().decode()
+
+
+def check_reciprocal(first_bits, last_bits, stream=None) -> int:
+    """Number of floats in the bit range whose projection reciprocal differs
+    from the IEEE quotient (synchronises)."""
+    import torch
+    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    _check(lib().pcr_check_reciprocal(first_bits, last_bits, _ptr(out), _stream(stream)))
+    return int(out.item())
 
 
 def fb_bytes(w, h, variant) -> int:

@@ -100,10 +100,11 @@ class GpuBackend:
     device tensor, written directly by the batch's resolve."""
 
     def __init__(self, clouds, budget_bytes: int, capacity: int = 16, plans_per_cloud: int = 2,
-                 tune=None, device="cuda"):
+                 tune=None, device="cuda", min_plan_views: int = 2):
         import torch
         self.torch = torch
         self.device = device
+        self.min_plan_views = min_plan_views
         self.clouds = clouds
         self.capacity = capacity
         self.arena_mem = torch.empty(budget_bytes, dtype=torch.uint8, device=device)
@@ -131,11 +132,21 @@ class GpuBackend:
 
     def launch(self, cloud: int, slot: int, reqs, offsets, images):
         plan, stream, _ = self.slots[cloud][slot]
-        views = [pcr.make_view(r.mvp, r.w, r.h, r.variant, self.base + off, img)
-                 for r, off, img in zip(reqs, offsets, images)]
         for img in images:
             img.record_stream(stream)
-        plan.launch(views, stream=stream)
+        if len(reqs) < self.min_plan_views:
+            # Too few views to share the point stream: the single-view path
+            # (same images), enqueued without any host synchronisation.
+            for r, off, img in zip(reqs, offsets, images):
+                v = pcr.DEDUP if r.variant == pcr.BASIC else r.variant
+                fb = self.base + off
+                pcr.fb_clear(fb, r.w, r.h, v, stream=stream)
+                pcr.render(self.clouds[cloud], r.mvp, r.w, r.h, v, fb, stream=stream)
+                pcr.resolve(fb, r.w, r.h, v, out=img, stream=stream)
+        else:
+            views = [pcr.make_view(r.mvp, r.w, r.h, r.variant, self.base + off, img)
+                     for r, off, img in zip(reqs, offsets, images)]
+            plan.launch(views, stream=stream)
         ev = self.torch.cuda.Event()
         ev.record(stream)
         self.slots[cloud][slot][2] = ev

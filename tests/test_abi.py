@@ -57,7 +57,7 @@ def test_fb_bytes():
 @pytest.mark.parametrize("variant,msg", [
     (3, "unknown variant"),
     (pcr.BASIC | (1 << 20), "flag bits"),
-    (pcr.HQ | pcr.F_REDUCE, "flag bits"),
+    (pcr.DEDUP | pcr.F_HQ_COLOR, "flag bits"),
     (pcr.DEDUP | pcr.F_PLAIN | pcr.F_LDS, "PLAIN"),
 ])
 def test_render_rejects_bad_variants(variant, msg):
