@@ -61,6 +61,8 @@ def _declare(lib):
         "oracle_render_hq_color": (None, [P, U64, P, U32, U32, P, P, P]),
         "oracle_render_hq": (None, [P, U64, P, U32, U32, P, P, P]),
         "oracle_resolve_hq": (None, [P, P, U32, U32, P]),
+        "oracle_resolve_depth_basic": (None, [P, U32, U32, I32, F, F, F, P]),
+        "oracle_resolve_depth_hq": (None, [P, U32, U32, I32, F, F, F, P]),
         "oracle_splitmix64": (U64, [U64, U64]),
         "oracle_bbox": (None, [P, U64, P, P]),
         "oracle_morton_interleave": (U64, [U32, U32, U32]),
@@ -188,6 +190,20 @@ class Oracle:
         BA = np.ascontiguousarray(BA, dtype=np.uint64)
         out = np.empty(W * H, np.uint32)
         self.lib.oracle_resolve_hq(_ptr(RG), _ptr(BA), W, H, _ptr(out))
+        return out
+
+    def resolve_depth_basic(self, fb, W, H, mode=0, a=0.0, b=0.0, empty=float("inf")):
+        """Depth image (float32[W*H]) of a basic framebuffer: w, or a + b/w."""
+        fb = np.ascontiguousarray(fb, dtype=np.uint64)
+        out = np.empty(W * H, np.float32)
+        self.lib.oracle_resolve_depth_basic(_ptr(fb), W, H, mode, a, b, empty, _ptr(out))
+        return out
+
+    def resolve_depth_hq(self, D, W, H, mode=0, a=0.0, b=0.0, empty=float("inf")):
+        """Depth image (float32[W*H]) of an HQ depth buffer: w, or a + b/w."""
+        D = np.ascontiguousarray(D, dtype=np.uint32)
+        out = np.empty(W * H, np.float32)
+        self.lib.oracle_resolve_depth_hq(_ptr(D), W, H, mode, a, b, empty, _ptr(out))
         return out
 
     # -- orders ---------------------------------------------------------------

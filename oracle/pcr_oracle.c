@@ -201,6 +201,44 @@ void oracle_resolve_hq(const uint64_t *RG, const uint64_t *BA, uint32_t W, uint3
     }
 }
 
+/* ---- depth output of the resolve (Sec. 3.1, closing paragraph) --------- */
+
+/* The stored depth is the linear depth w itself.  For hybrid rendering the
+ * resolve may also emit a conventional depth value: for a perspective
+ * projection that value is an affine function of 1/w, a + b * (1/w) (window
+ * depth in [0,1] with a = f/(f-n), b = -f*n/(f-n); reverse-z with
+ * a = -n/(f-n), b = f*n/(f-n)).  One correctly rounded reciprocal, then one
+ * product and one sum, each rounded once.  mode 0 = linear, 1 = a + b/w.
+ * A pixel nothing landed on gets `empty`. */
+static float depth_value(float w, int mode, float a, float b)
+{
+    if (mode == 0)
+        return w;
+    float rw = 1.0f / w;
+    float t = b * rw;
+    return a + t;
+}
+
+void oracle_resolve_depth_basic(const uint64_t *fb, uint32_t W, uint32_t H, int mode,
+                                float a, float b, float empty, float *out)
+{
+    for (uint64_t p = 0; p < (uint64_t)W * H; ++p) {
+        if (fb[p] == 0xFFFFFFFFFFFFFFFFull) {
+            out[p] = empty;
+            continue;
+        }
+        out[p] = depth_value(u2f((uint32_t)(fb[p] >> 32)), mode, a, b);
+    }
+}
+
+/* HQ: the depth of a pixel is the closest depth of its depth pass. */
+void oracle_resolve_depth_hq(const uint32_t *D, uint32_t W, uint32_t H, int mode,
+                             float a, float b, float empty, float *out)
+{
+    for (uint64_t p = 0; p < (uint64_t)W * H; ++p)
+        out[p] = D[p] == 0xFFFFFFFFu ? empty : depth_value(u2f(D[p]), mode, a, b);
+}
+
 /* ---- vertex orders (Sec. 4, Sec. 5) ------------------------------------ */
 
 /* SplitMix64: the k-th output (k = 0, 1, ...) of the generator seeded with

@@ -486,6 +486,103 @@ def check_golden_scene(orc):
     assert hashlib.sha256(perm.tobytes()).hexdigest() == g["morton_shuffle_sha256"]
 
 
+# ---------------------------------------------------------------------------
+# Depth output of the resolve (Sec. 3.1, closing paragraph)
+# ---------------------------------------------------------------------------
+
+def gl_perspective64(fovy_deg, aspect, near, far):
+    """The usual OpenGL projection matrix, float64, row-major."""
+    f = 1.0 / math.tan(math.radians(fovy_deg) / 2)
+    return np.array([[f / aspect, 0, 0, 0], [0, f, 0, 0],
+                     [0, 0, (far + near) / (near - far), 2 * far * near / (near - far)],
+                     [0, 0, -1, 0]], np.float64)
+
+
+def window_depth64(P, w):
+    """Window depth in [0,1] that the fixed-function pipeline derives from
+    clip z / clip w for view-space points at distance w in front of the camera."""
+    v = np.stack([np.zeros_like(w), np.zeros_like(w), -w, np.ones_like(w)])
+    c = P @ v
+    return (c[2] / c[3] + 1.0) / 2.0
+
+
+def check_depth_linear(orc):
+    """The linear depth of a pixel is the w of its closest point; uncovered
+    pixels get the caller's value (hand case: w = z, pixel centres)."""
+    W, H = 4, 4
+    m = identity(m14=1.0, m15=0.0)
+    cells = {(0, 0): [3.0, 1.5, 2.0], (3, 1): [0.25], (2, 3): [7.0, 7.5]}
+    xyz, cols = [], []
+    for (px, py), zs in cells.items():
+        X, Y = (px + 0.5) / (W / 2) - 1, (py + 0.5) / (H / 2) - 1
+        for z in zs:
+            xyz.append((X * z, Y * z, z))
+            cols.append(0x11223344)
+    pts = make_points(xyz, cols)
+    fb = orc.render_basic(pts, m, W, H)
+    out = orc.resolve_depth_basic(fb, W, H, 0, 0.0, 0.0, -1.0)
+    want = np.full(W * H, -1.0, np.float32)
+    for (px, py), zs in cells.items():
+        want[py * W + px] = min(zs)
+    assert np.array_equal(out, want), out
+    D, _, _ = orc.render_hq(pts, m, W, H)
+    assert np.array_equal(orc.resolve_depth_hq(D, W, H, 0, 0.0, 0.0, -1.0), want)
+
+
+def check_depth_window(orc):
+    """With a = f/(f-n), b = -f*n/(f-n) the hyperbolic depth is the window
+    depth of an OpenGL perspective projection (float64 through the matrix),
+    within the rounding bound of three float32 operations and two rounded
+    coefficients; with the reverse-z coefficients it is one minus that.
+    Both are monotone in w, and the near and far planes map to 0 and 1."""
+    u = 2.0 ** -24
+    rng = np.random.default_rng(21)
+    for near, far in ((0.1, 1000.0), (1.0, 100.0), (0.5, 5e4)):
+        P = gl_perspective64(60.0, 16 / 9, near, far)
+        w = np.sort(np.concatenate([[near, far], near * (far / near) ** rng.random(2000)]))
+        w = w.astype(np.float32)
+        fb = (w.view(np.uint32).astype(np.uint64) << np.uint64(32)) | np.uint64(0xFF00FF00)
+        n = len(w)
+        w64 = w.astype(np.float64)
+        exact = window_depth64(P, w64)
+        for reverse in (False, True):
+            a64 = -near / (far - near) if reverse else far / (far - near)
+            b64 = far * near / (far - near) * (1 if reverse else -1)
+            a, b = float(np.float32(a64)), float(np.float32(b64))
+            got = orc.resolve_depth_basic(fb, n, 1, 1, a, b, -1.0).astype(np.float64)
+            want = 1.0 - exact if reverse else exact
+            bound = 2 * u * (abs(a64) + 2 * np.abs(b64 / w64) + np.abs(want)) + 1e-12
+            assert np.all(np.abs(got - want) <= bound), (near, far, reverse, np.max(np.abs(got - want) - bound))
+            d = np.diff(got)
+            assert np.all(d <= 0) if reverse else np.all(d >= 0)
+            # the planes themselves, after rounding near and far to float32
+            tol = 8 * u * (abs(a64) + abs(b64) / near)
+            assert abs(got[0] - (1.0 if reverse else 0.0)) <= tol, (near, far, reverse, got[0])
+            assert abs(got[-1] - (0.0 if reverse else 1.0)) <= tol, (near, far, reverse, got[-1])
+
+
+def check_depth_dyadic(orc):
+    """Dyadic coefficients and depths: every step is exact."""
+    w = np.array([0.5, 0.25, 2.0, 1.0, 8.0], np.float32)
+    fb = (w.view(np.uint32).astype(np.uint64) << np.uint64(32)) | np.uint64(7)
+    fb = np.concatenate([fb, [np.uint64(FULL)]])
+    got = orc.resolve_depth_basic(fb, 6, 1, 1, 0.5, -0.25, 3.0)
+    assert got.tolist() == [0.0, -0.5, 0.375, 0.25, 0.46875, 3.0], got
+
+
+def check_depth_hq_equals_basic(orc):
+    """The HQ depth pass keeps the same closest depth as the basic key, so
+    both depth images agree in every mode."""
+    pts, m, W, H = _dense_tiny_cloud(23)
+    fb = orc.render_basic(pts, m, W, H)
+    D, _, _ = orc.render_hq(pts, m, W, H)
+    for mode, a, b in ((0, 0.0, 0.0), (1, 1.0009995, -0.10004998)):
+        x = orc.resolve_depth_basic(fb, W, H, mode, a, b, -2.0)
+        y = orc.resolve_depth_hq(D, W, H, mode, a, b, -2.0)
+        assert np.array_equal(x, y)
+        assert np.any(x == -2.0) and np.any(x != -2.0)
+
+
 ALL_CHECKS = [
     check_hand_cases, check_projection_fp64, check_projection_dyadic, check_projection_rounding,
     check_basic_brute_force, check_basic_permutation, check_basic_accumulate,
@@ -494,4 +591,5 @@ ALL_CHECKS = [
     check_hq_permutation,
     check_splitmix64, check_morton_interleave, check_morton_quantisation, check_reorder,
     check_reorder_edges, check_image_order_invariance,
+    check_depth_linear, check_depth_window, check_depth_dyadic, check_depth_hq_equals_basic,
 ]

@@ -50,6 +50,14 @@ MUTANTS = [
     ("splitmix counter from 0", [("seed + (k + 1) * 0x9E3779B97F4A7C15ull", "seed + k * 0x9E3779B97F4A7C15ull")], []),
     ("batches not moved", [("uint64_t s = b * batch,", "uint64_t s = r * batch,")], []),
     ("last partial batch dropped", [("uint64_t nb = (n + batch - 1) / batch;", "uint64_t nb = n / batch;")], []),
+    ("depth without reciprocal", [("float rw = 1.0f / w;", "float rw = w;")], []),
+    ("depth offset subtracted", [("return a + t;", "return a - t;")], []),
+    ("depth coefficients swapped", [("float t = b * rw;", "float t = a * rw;"), ("return a + t;", "return b + t;")],
+     []),
+    ("linear depth from the colour word", [("depth_value(u2f((uint32_t)(fb[p] >> 32))", "depth_value(u2f((uint32_t)fb[p])")],
+     []),
+    ("uncovered depth 0", [("out[p] = empty;", "out[p] = 0.0f;")], []),
+    ("hq depth empty test on 0", [("D[p] == 0xFFFFFFFFu ? empty", "D[p] == 0u ? empty")], []),
 ]
 
 
