@@ -157,6 +157,43 @@ int pcr_render(const pcr_point *pts, uint64_t n, const float mvp[16], uint32_t w
 int pcr_render_ex(const pcr_point *pts, uint64_t n, const float mvp[16], uint32_t w, uint32_t h,
                   int variant, void *fb, const pcr_tune *tune, void *stream);
 
+/* One chunk of a many-chunk frame: a separate point buffer (e.g. one node of a
+ * level-of-detail octree).  16 bytes, as stored in a device array. */
+typedef struct pcr_chunk {
+    const pcr_point *pts; /* device, 16-byte aligned */
+    uint64_t n;           /* points in the chunk */
+} pcr_chunk;
+
+/* Largest point count of one chunk; larger chunks are skipped. */
+#define PCR_CHUNK_MAX_POINTS (1ull << 36)
+
+/* Device scratch that pcr_render_chunks needs for nchunks chunks
+ * (0 if nchunks is 0 or above 2^24). */
+size_t pcr_chunks_scratch_bytes(uint32_t nchunks);
+
+/* Renders many separate point buffers into one framebuffer with one
+ * persistent launch per geometry pass (Sec. 5.4: level-of-detail structures
+ * draw thousands of small buffers per frame; per-buffer dispatches are what
+ * makes them slow).  The result is the frame of the concatenation of the
+ * chunks (basic, dedup and HQ alike; the order of points does not change a
+ * closest-point image or an HQ sum).
+ *   chunks     device array of nchunks pcr_chunk records, read on the device
+ *              (so a GPU-side selection can write it).  A chunk with a NULL or
+ *              misaligned pointer, or more than PCR_CHUNK_MAX_POINTS points,
+ *              is skipped (contributes nothing); n == 0 is an empty chunk.
+ *   nchunks    at most 2^24; 0 is a no-op.
+ *   scratch    device, at least pcr_chunks_scratch_bytes(nchunks) bytes,
+ *              256-byte aligned; overwritten (chunk start offsets).
+ *   variant    PCR_BASIC, PCR_DEDUP or PCR_HQ, optionally with one PCR_F_HQ_*
+ *              pass bit; the other flag bits give PCR_EUNSUPPORTED.
+ *   tune       as pcr_render_ex (may be NULL); grid 0 = as many workgroups as
+ *              are resident at once.
+ * Errors: PCR_EINVAL (as pcr_render, plus NULL chunks with nchunks > 0,
+ * nchunks > 2^24), PCR_ENOMEM (scratch too small). */
+int pcr_render_chunks(const pcr_chunk *chunks, uint32_t nchunks, const float mvp[16], uint32_t w,
+                      uint32_t h, int variant, void *fb, void *scratch, size_t scratch_bytes,
+                      const pcr_tune *tune, void *stream);
+
 /* Resolve pass (Sec. 3.1 second listing, Sec. 3.5 resolve listing).
  *   rgba_out  device, uint32[W*H].
  * Basic/dedup: the colour word of the stored key, 0 where nothing landed.
@@ -164,6 +201,29 @@ int pcr_render_ex(const pcr_point *pts, uint64_t n, const float mvp[16], uint32_
  * the count is 0. */
 int pcr_resolve(const void *fb, uint32_t w, uint32_t h, int variant, uint32_t *rgba_out,
                 void *stream);
+
+/* Depth output modes of pcr_resolve_depth. */
+enum { PCR_DEPTH_LINEAR = 0, PCR_DEPTH_HYPERBOLIC = 1 };
+
+/* Resolve with a depth image (Sec. 3.1, closing paragraph: the stored depth is
+ * the linear clip-space w, usable for depth buffering as it is; conventional
+ * depth values, e.g. for hybrid rendering with triangles, are derived in the
+ * resolve).
+ *   mode       PCR_DEPTH_LINEAR: depth_out = w of the pixel's closest point.
+ *              PCR_DEPTH_HYPERBOLIC: depth_out = a + b * (1/w) with a correctly
+ *              rounded reciprocal, then one product and one sum, each rounded
+ *              once (no fused multiply-add).  For a perspective projection with
+ *              near n and far f: a = f/(f-n), b = -f*n/(f-n) gives the window
+ *              depth in [0,1] (0 at the near plane); a = -n/(f-n), b = f*n/(f-n)
+ *              gives reverse-z (1 at the near plane).
+ *   empty      value written where nothing landed.
+ *   rgba_out   device uint32[W*H] or NULL: when given, the pcr_resolve image,
+ *              written in the same pass.
+ *   depth_out  device float[W*H], 4-byte aligned.
+ * HQ: the depth of a pixel is the closest depth kept by the depth pass.
+ * Errors: as pcr_resolve; PCR_EINVAL for an unknown mode or a NULL depth_out. */
+int pcr_resolve_depth(const void *fb, uint32_t w, uint32_t h, int variant, int mode, float a,
+                      float b, float empty, uint32_t *rgba_out, float *depth_out, void *stream);
 
 /* Device scratch needed by pcr_reorder for n points (0 if n is too large). */
 size_t pcr_reorder_scratch_bytes(uint64_t n, int order, uint32_t batch);

@@ -302,19 +302,77 @@ __device__ __forceinline__ void load_tile(const u32x4 *__restrict__ pts, uint64_
     }
 }
 
+// Point sources of the render kernels.  FlatSrc: one contiguous buffer (the
+// kernel's `pts` argument).  ChunkSrc: the concatenation of many separate
+// buffers (level-of-detail chunks, Sec. 5.4); the tiles run over the virtual
+// concatenation, so small chunks share tiles and no lane idles at a chunk's
+// end.  start[c] is the first virtual index of chunk c, start[nchunks] the
+// total; both are written on the device by k_chunk_starts, so the tile count
+// is only known inside the kernel (setup()).
+struct FlatSrc {
+    static constexpr bool chunked = false;
+    __device__ __forceinline__ void setup(Tiles &, uint32_t) const {}
+    template <int PPT>
+    __device__ __forceinline__ void load(const u32x4 *__restrict__ pts, uint64_t first, uint32_t wg, uint64_t n,
+                                         u32x4 (&p)[PPT]) const {
+        load_tile<PPT>(pts, first, wg, n, p);
+    }
+};
+
+struct ChunkSrc {
+    static constexpr bool chunked = true;
+    const pcr_chunk *chunks;
+    const uint64_t *start;
+    uint32_t nchunks;
+
+    // Every workgroup takes tiles b, b + grid, ... (grid a multiple of 8, so
+    // a workgroup stays on one XCD) through the XCD-contiguous tile mapping.
+    __device__ __forceinline__ void setup(Tiles &tl, uint32_t T) const {
+        const uint64_t n = start[nchunks];
+        tl.n = n;
+        tl.ntiles = (n + T - 1) / T;
+        tl.nblocks = (tl.ntiles + 7) / 8 * 8;
+        tl.remap = 1;
+    }
+    template <int PPT>
+    __device__ __forceinline__ void load(const u32x4 *__restrict__, uint64_t first, uint32_t wg, uint64_t n,
+                                         u32x4 (&p)[PPT]) const {
+        // Chunk of the tile's first point: the last c with start[c] <= first
+        // (uniform binary search; start[nchunks] = n > first).
+        uint32_t lo = 0, hi = nchunks;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) / 2;
+            if (start[mid] <= first) lo = mid;
+            else hi = mid;
+        }
+        // Each lane walks forward to the chunk of its own points (indices
+        // grow with j; lanes past the end take the last point, discarded by
+        // the caller).
+        uint32_t c = lo;
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            uint64_t g = first + (uint64_t)(j * wg + threadIdx.x);
+            if (g >= n) g = n - 1;
+            while (start[c + 1] <= g) ++c;
+            p[j] = load_point((const u32x4 *)chunks[c].pts + (g - start[c]));
+        }
+    }
+};
+
 // Basic closest-point render (Sec. 3.1), optionally with the early depth test
 // (Sec. 3.2) and the wavefront reduction (Sec. 3.3).
-template <int PPT, bool EARLYZ, bool REDUCE>
+template <int PPT, bool EARLYZ, bool REDUCE, class Src>
 __global__ __launch_bounds__(1024) void k_basic(const u32x4 *__restrict__ pts, Tiles tl, View v,
-                                                u64 *__restrict__ fb) {
+                                                u64 *__restrict__ fb, Src src) {
     const uint32_t wg = blockDim.x;
+    if constexpr (Src::chunked) src.setup(tl, wg * PPT);
     for (uint64_t b = blockIdx.x; b < tl.nblocks; b += gridDim.x) {
         uint64_t t;
         if (!tl.tile(b, t)) continue;
         const uint64_t first = t * wg * PPT;
         const uint64_t base = first + threadIdx.x;
         u32x4 p[PPT];
-        load_tile<PPT>(pts, first, wg, tl.n, p);
+        src.template load<PPT>(pts, first, wg, tl.n, p);
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             uint32_t dbits;
@@ -339,12 +397,13 @@ __device__ __forceinline__ void direct_min(V *fb, uint32_t pid, V val, bool earl
     }
 }
 
-template <typename V, int PPT, bool EARLYZ, bool REDUCE>
+template <typename V, int PPT, bool EARLYZ, bool REDUCE, class Src>
 __global__ __launch_bounds__(1024) void k_dedup(const u32x4 *__restrict__ pts, Tiles tl, View v,
-                                                V *__restrict__ fb, uint32_t hbits) {
+                                                V *__restrict__ fb, uint32_t hbits, Src src) {
     extern __shared__ __align__(16) unsigned char smem[];
     Lds<V> L(smem, hbits);
     const uint32_t wg = blockDim.x;
+    if constexpr (Src::chunked) src.setup(tl, wg * PPT);
     const uint32_t HS = 1u << hbits;
     for (uint32_t s = threadIdx.x; s < HS; s += wg) {
         L.tag[s] = kEmptyPid;
@@ -359,7 +418,7 @@ __global__ __launch_bounds__(1024) void k_dedup(const u32x4 *__restrict__ pts, T
         const uint64_t first = t * wg * PPT;
         const uint64_t base = first + threadIdx.x;
         u32x4 p[PPT];
-        load_tile<PPT>(pts, first, wg, tl.n, p);
+        src.template load<PPT>(pts, first, wg, tl.n, p);
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             uint32_t dbits;
@@ -427,12 +486,13 @@ __global__ __launch_bounds__(1024) void k_hq_depth(const u32x4 *__restrict__ pts
 // HQ colour pass (Sec. 3.5): a point within 1% of its pixel's closest depth
 // (depth <= fl32(closest * 1.01f)) adds (r << 32 | g) and (b << 32 | 1) to the
 // pixel's two 64-bit sums.
-template <int PPT, bool LDS>
+template <int PPT, bool LDS, class Src>
 __global__ __launch_bounds__(1024) void k_hq_color(const u32x4 *__restrict__ pts, Tiles tl, View v,
                                                    const uint32_t *__restrict__ D,
-                                                   u64 *__restrict__ S, uint32_t hbits) {
+                                                   u64 *__restrict__ S, uint32_t hbits, Src src) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t wg = blockDim.x;
+    if constexpr (Src::chunked) src.setup(tl, wg * PPT);
     Lds<Sum2> L(smem, hbits);
     if (LDS) {
         for (uint32_t s = threadIdx.x; s < (1u << hbits); s += wg) {
@@ -450,7 +510,7 @@ __global__ __launch_bounds__(1024) void k_hq_color(const u32x4 *__restrict__ pts
         const uint64_t first = t * wg * PPT;
         const uint64_t base = first + threadIdx.x;
         u32x4 p[PPT];
-        load_tile<PPT>(pts, first, wg, tl.n, p);
+        src.template load<PPT>(pts, first, wg, tl.n, p);
         // Project every point first, then read all their closest depths back
         // to back (one round trip for the tile instead of one per point).
         uint32_t pids[PPT], dbs[PPT], dref[PPT];
@@ -511,18 +571,56 @@ __global__ __launch_bounds__(256) void k_resolve_basic(const u64 *__restrict__ f
     }
 }
 
+// Integer average of one pixel's sums; s = {G sum, R sum, count, B sum}.
+__device__ __forceinline__ uint32_t hq_colour(u32x4 s) {
+    const uint32_t c = s.z;
+    if (c == 0) return 0u;
+    uint32_t r = s.y / c, g = s.x / c, b = s.w / c;
+    return (r & 0xFFu) | (g & 0xFFu) << 8 | (b & 0xFFu) << 16 | 0xFF000000u;
+}
+
 __global__ __launch_bounds__(256) void k_resolve_hq(const u32x4 *__restrict__ S,
                                                     uint32_t *__restrict__ out, uint64_t npix) {
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npix; i += stride)
+        out[i] = hq_colour(S[i]);
+}
+
+// Depth output (Sec. 3.1, closing paragraph): the stored linear depth w, or
+// a + b * (1/w) (window or reverse-z depth of a perspective projection), with
+// the projection's correctly rounded reciprocal and no contraction.
+__device__ __forceinline__ float depth_value(uint32_t dbits, int mode, float a, float b) {
+    const float w = __uint_as_float(dbits);
+    if (mode == PCR_DEPTH_LINEAR) return w;
+    const float t = b * recip_rn(w);
+    return a + t;
+}
+
+__global__ __launch_bounds__(256) void k_resolve_basic_depth(const u64 *__restrict__ fb,
+                                                             uint32_t *__restrict__ out,
+                                                             float *__restrict__ depth, uint64_t npix,
+                                                             int mode, float a, float b, float empty) {
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npix; i += stride) {
-        u32x4 s = S[i];  // {G sum, R sum, count, B sum}
-        uint32_t c = s.z;
-        uint32_t o = 0;
-        if (c != 0) {
-            uint32_t r = s.y / c, g = s.x / c, b = s.w / c;
-            o = (r & 0xFFu) | (g & 0xFFu) << 8 | (b & 0xFFu) << 16 | 0xFF000000u;
-        }
-        out[i] = o;
+        const u64 k = fb[i];
+        const bool hit = k != kEmptyKey;
+        if (out) out[i] = hit ? (uint32_t)k : 0u;
+        const float d = depth_value((uint32_t)(k >> 32), mode, a, b);
+        depth[i] = hit ? d : empty;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_resolve_hq_depth(const uint32_t *__restrict__ D,
+                                                          const u32x4 *__restrict__ S,
+                                                          uint32_t *__restrict__ out,
+                                                          float *__restrict__ depth, uint64_t npix,
+                                                          int mode, float a, float b, float empty) {
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npix; i += stride) {
+        if (out) out[i] = hq_colour(S[i]);
+        const uint32_t db = D[i];
+        const float d = depth_value(db, mode, a, b);
+        depth[i] = db != 0xFFFFFFFFu ? d : empty;
     }
 }
 
@@ -587,8 +685,9 @@ struct BasicL {
                 return fail(PCR_EINVAL, "tile of %u points needs %zu bytes of LDS", T, sm);
 #define PCR_DD(E, R)                                                                                    \
     do {                                                                                                \
-        if (int rc_ = allow_lds((const void *)&k_dedup<u64, P, E, R>, sm)) return rc_;                  \
-        hipLaunchKernelGGL((k_dedup<u64, P, E, R>), dim3(grid), dim3(L.sh.wg), sm, L.s, L.pts, tl, L.v, fb, hb); \
+        if (int rc_ = allow_lds((const void *)&k_dedup<u64, P, E, R, FlatSrc>, sm)) return rc_;         \
+        hipLaunchKernelGGL((k_dedup<u64, P, E, R, FlatSrc>), dim3(grid), dim3(L.sh.wg), sm, L.s, L.pts, tl, L.v, fb, \
+                           hb, FlatSrc{});                                                             \
     } while (0)
             if (ez && rd) PCR_DD(true, true);
             else if (ez) PCR_DD(true, false);
@@ -596,7 +695,8 @@ struct BasicL {
             else PCR_DD(false, false);
 #undef PCR_DD
         } else {
-#define PCR_BB(E, R) hipLaunchKernelGGL((k_basic<P, E, R>), dim3(grid), dim3(L.sh.wg), 0, L.s, L.pts, tl, L.v, fb)
+#define PCR_BB(E, R) \
+    hipLaunchKernelGGL((k_basic<P, E, R, FlatSrc>), dim3(grid), dim3(L.sh.wg), 0, L.s, L.pts, tl, L.v, fb, FlatSrc{})
             if (ez && rd) PCR_BB(true, true);
             else if (ez) PCR_BB(true, false);
             else if (rd) PCR_BB(false, true);
@@ -622,8 +722,9 @@ struct DepthL {
                 return fail(PCR_EINVAL, "tile of %u points needs %zu bytes of LDS", T, sm);
 #define PCR_DD(E, R)                                                                                    \
     do {                                                                                                \
-        if (int rc_ = allow_lds((const void *)&k_dedup<uint32_t, P, E, R>, sm)) return rc_;             \
-        hipLaunchKernelGGL((k_dedup<uint32_t, P, E, R>), dim3(grid), dim3(L.sh.wg), sm, L.s, L.pts, tl, L.v, D, hb); \
+        if (int rc_ = allow_lds((const void *)&k_dedup<uint32_t, P, E, R, FlatSrc>, sm)) return rc_;    \
+        hipLaunchKernelGGL((k_dedup<uint32_t, P, E, R, FlatSrc>), dim3(grid), dim3(L.sh.wg), sm, L.s, L.pts, tl, L.v, \
+                           D, hb, FlatSrc{});                                                          \
     } while (0)
             if (ez && rd) PCR_DD(true, true);
             else if (ez) PCR_DD(true, false);
@@ -652,14 +753,123 @@ struct ColorL {
             size_t sm = lds_bytes(hb, 16);
             if (sm > max_lds())
                 return fail(PCR_EINVAL, "tile of %u points needs %zu bytes of LDS", T, sm);
-            if (int rc = allow_lds((const void *)&k_hq_color<P, true>, sm)) return rc;
-            hipLaunchKernelGGL((k_hq_color<P, true>), dim3(grid), dim3(L.sh.wg), sm, L.s, L.pts, tl, L.v, D,
-                               S, hb);
+            if (int rc = allow_lds((const void *)&k_hq_color<P, true, FlatSrc>, sm)) return rc;
+            hipLaunchKernelGGL((k_hq_color<P, true, FlatSrc>), dim3(grid), dim3(L.sh.wg), sm, L.s, L.pts, tl, L.v, D,
+                               S, hb, FlatSrc{});
         } else {
-            hipLaunchKernelGGL((k_hq_color<P, false>), dim3(grid), dim3(L.sh.wg), 0, L.s, L.pts, tl, L.v, D,
-                               S, 1u);
+            hipLaunchKernelGGL((k_hq_color<P, false, FlatSrc>), dim3(grid), dim3(L.sh.wg), 0, L.s, L.pts, tl, L.v, D,
+                               S, 1u, FlatSrc{});
         }
         PCR_LAUNCHED();
+        return PCR_OK;
+    }
+};
+
+// ---- many-chunk frames ------------------------------------------------------
+
+// Exclusive prefix of the chunk sizes into start[0..nchunks] (one workgroup;
+// a skipped chunk counts 0 points).
+__device__ __forceinline__ uint64_t shfl_up64(uint64_t x, uint32_t d) {
+    uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)x, d, 64);
+    uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(x >> 32), d, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__global__ __launch_bounds__(1024) void k_chunk_starts(const pcr_chunk *__restrict__ chunks, uint32_t nchunks,
+                                                       uint64_t *__restrict__ start) {
+    __shared__ uint64_t wtot[16];
+    const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint64_t carry = 0;
+    for (uint32_t base = 0; base < nchunks; base += blockDim.x) {
+        const uint32_t i = base + threadIdx.x;
+        uint64_t c = 0;
+        if (i < nchunks) {
+            const pcr_chunk ch = chunks[i];
+            const bool ok = ch.pts != nullptr && ((uintptr_t)ch.pts & 15u) == 0 && ch.n <= PCR_CHUNK_MAX_POINTS;
+            c = ok ? ch.n : 0;
+        }
+        uint64_t x = c;  // inclusive scan over the wavefront
+        for (uint32_t d = 1; d < 64; d <<= 1) {
+            const uint64_t y = shfl_up64(x, d);
+            if (lane >= d) x += y;
+        }
+        if (lane == 63) wtot[wid] = x;
+        __syncthreads();
+        uint64_t before = carry, total = carry;
+        for (uint32_t k = 0; k < nw; ++k) {
+            if (k < wid) before += wtot[k];
+            total += wtot[k];
+        }
+        if (i < nchunks) start[i] = before + x - c;
+        carry = total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) start[nchunks] = carry;
+}
+
+// Workgroups resident at once (a multiple of 8), unless the caller fixed it.
+uint32_t persistent_grid(const void *fn, uint32_t wg, size_t sm, uint32_t want) {
+    if (want) return want;
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, (int)wg, sm) != hipSuccess || per < 1) per = 1;
+    uint32_t g = (uint32_t)per * (uint32_t)device_cus() / 8u * 8u;
+    return g < 8u ? 8u : g;
+}
+
+struct ChunkLaunch {
+    ChunkSrc src;
+    View v;
+    void *fb;
+    int fam;
+    uint32_t pass;  // HQ passes to run
+    Shape sh;
+    uint32_t w, h;
+    hipStream_t s;
+};
+
+template <int P>
+struct ChunkL {
+    static int run(const ChunkLaunch &C) {
+        const uint32_t wg = C.sh.wg, T = wg * P, hb = lds_hbits(T, C.sh.slots);
+        const Tiles tl{};
+        if (C.fam == PCR_BASIC) {
+            const void *fn = (const void *)&k_basic<P, false, false, ChunkSrc>;
+            hipLaunchKernelGGL((k_basic<P, false, false, ChunkSrc>), dim3(persistent_grid(fn, wg, 0, C.sh.grid)),
+                               dim3(wg), 0, C.s, nullptr, tl, C.v, (u64 *)C.fb, C.src);
+            PCR_LAUNCHED();
+            return PCR_OK;
+        }
+        if (C.fam == PCR_DEDUP) {
+            const size_t sm = lds_bytes(hb, 8);
+            if (sm > max_lds()) return fail(PCR_EINVAL, "tile of %u points needs %zu bytes of LDS", T, sm);
+            const void *fn = (const void *)&k_dedup<u64, P, false, true, ChunkSrc>;
+            if (int rc = allow_lds(fn, sm)) return rc;
+            hipLaunchKernelGGL((k_dedup<u64, P, false, true, ChunkSrc>), dim3(persistent_grid(fn, wg, sm, C.sh.grid)),
+                               dim3(wg), sm, C.s, nullptr, tl, C.v, (u64 *)C.fb, hb, C.src);
+            PCR_LAUNCHED();
+            return PCR_OK;
+        }
+        if (C.pass & PCR_F_HQ_DEPTH) {
+            const size_t sm = lds_bytes(hb, 4);
+            if (sm > max_lds()) return fail(PCR_EINVAL, "tile of %u points needs %zu bytes of LDS", T, sm);
+            const void *fn = (const void *)&k_dedup<uint32_t, P, false, true, ChunkSrc>;
+            if (int rc = allow_lds(fn, sm)) return rc;
+            hipLaunchKernelGGL((k_dedup<uint32_t, P, false, true, ChunkSrc>),
+                               dim3(persistent_grid(fn, wg, sm, C.sh.grid)), dim3(wg), sm, C.s, nullptr, tl, C.v,
+                               (uint32_t *)C.fb, hb, C.src);
+            PCR_LAUNCHED();
+        }
+        if (C.pass & PCR_F_HQ_COLOR) {
+            const size_t sm = lds_bytes(hb, 16);
+            if (sm > max_lds()) return fail(PCR_EINVAL, "tile of %u points needs %zu bytes of LDS", T, sm);
+            const void *fn = (const void *)&k_hq_color<P, true, ChunkSrc>;
+            if (int rc = allow_lds(fn, sm)) return rc;
+            const uint32_t *D = (const uint32_t *)C.fb;
+            u64 *S = (u64 *)((char *)C.fb + hq_depth_bytes(C.w, C.h));
+            hipLaunchKernelGGL((k_hq_color<P, true, ChunkSrc>), dim3(persistent_grid(fn, wg, sm, C.sh.grid)),
+                               dim3(wg), sm, C.s, nullptr, tl, C.v, D, S, hb, C.src);
+            PCR_LAUNCHED();
+        }
         return PCR_OK;
     }
 };
@@ -739,6 +949,43 @@ extern "C" int pcr_render(const pcr_point *pts, uint64_t n, const float mvp[16],
     return pcr_render_ex(pts, n, mvp, w, h, variant, fb, nullptr, stream);
 }
 
+extern "C" size_t pcr_chunks_scratch_bytes(uint32_t nchunks) {
+    if (nchunks == 0 || nchunks > (1u << 24)) return 0;
+    return ((size_t)8 * (nchunks + 1) + 255) / 256 * 256;
+}
+
+extern "C" int pcr_render_chunks(const pcr_chunk *chunks, uint32_t nchunks, const float mvp[16], uint32_t w,
+                                 uint32_t h, int variant, void *fb, void *scratch, size_t scratch_bytes,
+                                 const pcr_tune *tune, void *stream) {
+    int rc = check_image(w, h);
+    if (rc == PCR_OK) rc = check_variant(variant);
+    if (rc != PCR_OK) return rc;
+    const int fam = variant & 0xFF;
+    const uint32_t flags = (uint32_t)variant & ~0xFFu;
+    if ((flags & kFlagMask) != 0 || (fam != PCR_HQ && flags != 0))
+        return fail(PCR_EUNSUPPORTED, "chunked rendering takes the default form of each variant (flags 0x%x)", flags);
+    if (!mvp) return fail(PCR_EINVAL, "mvp is NULL");
+    if (!fb || ((uintptr_t)fb & 15)) return fail(PCR_EINVAL, "framebuffer must be a 16-byte aligned device pointer");
+    if (nchunks > (1u << 24)) return fail(PCR_EINVAL, "at most 2^24 chunks (got %u)", nchunks);
+    Shape sh;
+    rc = resolve_shape(tune, fam, sh);
+    if (rc != PCR_OK) return rc;
+    if (nchunks == 0) return PCR_OK;
+    if (!chunks || ((uintptr_t)chunks & 7)) return fail(PCR_EINVAL, "chunks must be an 8-byte aligned device pointer");
+    if (!scratch || ((uintptr_t)scratch & 15)) return fail(PCR_EINVAL, "scratch must be a 16-byte aligned device pointer");
+    const size_t need = pcr_chunks_scratch_bytes(nchunks);
+    if (scratch_bytes < need)
+        return fail(PCR_ENOMEM, "scratch holds %zu bytes, %u chunks need %zu", scratch_bytes, nchunks, need);
+    hipStream_t s = (hipStream_t)stream;
+    uint64_t *start = (uint64_t *)scratch;
+    hipLaunchKernelGGL(k_chunk_starts, dim3(1), dim3(1024), 0, s, chunks, nchunks, start);
+    PCR_LAUNCHED();
+    uint32_t pass = flags & kHqPassMask;
+    if (pass == 0) pass = kHqPassMask;
+    ChunkLaunch C{ChunkSrc{chunks, start, nchunks}, make_view(mvp, w, h), fb, fam, pass, sh, w, h, s};
+    return by_ppt<ChunkL>(sh.ppt, C);
+}
+
 extern "C" int pcr_resolve(const void *fb, uint32_t w, uint32_t h, int variant, uint32_t *rgba_out,
                            void *stream) {
     int rc = check_image(w, h);
@@ -755,6 +1002,33 @@ extern "C" int pcr_resolve(const void *fb, uint32_t w, uint32_t h, int variant, 
         hipLaunchKernelGGL(k_resolve_hq, dim3(grid), dim3(256), 0, s, S, rgba_out, px);
     } else {
         hipLaunchKernelGGL(k_resolve_basic, dim3(grid), dim3(256), 0, s, (const u64 *)fb, rgba_out, px);
+    }
+    PCR_LAUNCHED();
+    return PCR_OK;
+}
+
+extern "C" int pcr_resolve_depth(const void *fb, uint32_t w, uint32_t h, int variant, int mode, float a,
+                                 float b, float empty, uint32_t *rgba_out, float *depth_out, void *stream) {
+    int rc = check_image(w, h);
+    if (rc == PCR_OK) rc = check_variant(variant);
+    if (rc != PCR_OK) return rc;
+    if (mode != PCR_DEPTH_LINEAR && mode != PCR_DEPTH_HYPERBOLIC) return fail(PCR_EINVAL, "unknown depth mode %d", mode);
+    if (!fb || ((uintptr_t)fb & 15)) return fail(PCR_EINVAL, "framebuffer must be a 16-byte aligned device pointer");
+    if (!depth_out || ((uintptr_t)depth_out & 3))
+        return fail(PCR_EINVAL, "depth_out must be a 4-byte aligned device pointer");
+    if ((uintptr_t)rgba_out & 3) return fail(PCR_EINVAL, "rgba_out must be 4-byte aligned");
+    uint64_t px = (uint64_t)w * h;
+    uint64_t want = (px + 255) / 256;
+    uint32_t grid = (uint32_t)(want > 16384 ? 16384 : want);
+    hipStream_t s = (hipStream_t)stream;
+    if ((variant & 0xFF) == PCR_HQ) {
+        const uint32_t *D = (const uint32_t *)fb;
+        const u32x4 *S = (const u32x4 *)((const char *)fb + hq_depth_bytes(w, h));
+        hipLaunchKernelGGL(k_resolve_hq_depth, dim3(grid), dim3(256), 0, s, D, S, rgba_out, depth_out, px, mode,
+                           a, b, empty);
+    } else {
+        hipLaunchKernelGGL(k_resolve_basic_depth, dim3(grid), dim3(256), 0, s, (const u64 *)fb, rgba_out,
+                           depth_out, px, mode, a, b, empty);
     }
     PCR_LAUNCHED();
     return PCR_OK;

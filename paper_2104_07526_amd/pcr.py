@@ -28,6 +28,7 @@ F_PLAIN = 1 << 11
 F_HQ_DEPTH = 1 << 12
 F_HQ_COLOR = 1 << 13
 ORDER_MORTON, ORDER_MORTON_SHUFFLE, ORDER_SHUFFLE = 0, 1, 2
+DEPTH_LINEAR, DEPTH_HYPERBOLIC = 0, 1
 
 OK, EINVAL, EHIP, ENOMEM, EUNSUPPORTED = 0, -1, -2, -3, -4
 
@@ -61,6 +62,10 @@ def _declare(lib):
         "pcr_render": (I32, [P, U64, P, U32, U32, I32, P, P]),
         "pcr_render_ex": (I32, [P, U64, P, U32, U32, I32, P, P, P]),
         "pcr_resolve": (I32, [P, U32, U32, I32, P, P]),
+        "pcr_resolve_depth": (I32, [P, U32, U32, I32, I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                    P, P, P]),
+        "pcr_chunks_scratch_bytes": (SZ, [U32]),
+        "pcr_render_chunks": (I32, [P, U32, P, U32, U32, I32, P, P, SZ, P, P]),
         "pcr_reorder_scratch_bytes": (SZ, [U64, I32, U32]),
         "pcr_reorder": (I32, [P, P, P, U64, I32, U32, U64, P, SZ, P]),
         "pcr_batch_create": (I32, [P, P, U64, U32, P, P]),
@@ -171,6 +176,54 @@ def resolve(fb, w, h, variant, out=None, stream=None):
         out = torch.empty(w * h, dtype=torch.int32, device=fb.device)
     _check(lib().pcr_resolve(_ptr(fb), w, h, variant, _ptr(out), _stream(stream)))
     return out
+
+
+def chunks_scratch_bytes(nchunks) -> int:
+    return int(lib().pcr_chunks_scratch_bytes(nchunks))
+
+
+def chunk_table(chunks, device="cuda"):
+    """Device array of pcr_chunk records from (buffer or device address, point
+    count) pairs; a buffer may be a torch tensor (its data pointer is used)."""
+    import torch
+    rows = [[_ptr(b) or 0, int(n)] for b, n in chunks]
+    return torch.tensor(rows if rows else [[0, 0]], dtype=torch.int64).to(device)
+
+
+def render_chunks(table, nchunks, mvp, w, h, variant, fb, scratch=None, tune=None, stream=None):
+    """Renders the first ``nchunks`` records of a device chunk table into fb
+    (one persistent launch per geometry pass).  Returns the scratch buffer."""
+    import torch
+    if scratch is None:
+        scratch = torch.empty(max(chunks_scratch_bytes(nchunks), 256), dtype=torch.uint8, device=fb.device)
+    nbytes = scratch.numel() * scratch.element_size()
+    _check(lib().pcr_render_chunks(_ptr(table), nchunks, _mvp(mvp), w, h, variant, _ptr(fb), _ptr(scratch),
+                                   nbytes, _tune(tune), _stream(stream)))
+    return scratch
+
+
+def depth_coeffs(near, far, reverse=False):
+    """(a, b) for DEPTH_HYPERBOLIC: window depth in [0,1] of a perspective
+    projection with the given near and far planes (0 at near), or reverse-z
+    (1 at near).  Computed in float64, rounded once to float32."""
+    n, f = float(near), float(far)
+    if reverse:
+        a, b = -n / (f - n), f * n / (f - n)
+    else:
+        a, b = f / (f - n), -f * n / (f - n)
+    return float(np.float32(a)), float(np.float32(b))
+
+
+def resolve_depth(fb, w, h, variant, mode=DEPTH_LINEAR, a=0.0, b=0.0, empty=float("inf"), depth=None,
+                  rgba=None, stream=None):
+    """Depth image (float32 tensor [w*h]) and, when ``rgba`` is a tensor, the
+    colour image in the same pass.  Returns (depth, rgba)."""
+    import torch
+    if depth is None:
+        depth = torch.empty(w * h, dtype=torch.float32, device=fb.device)
+    _check(lib().pcr_resolve_depth(_ptr(fb), w, h, variant, mode, a, b, empty, _ptr(rgba), _ptr(depth),
+                                   _stream(stream)))
+    return depth, rgba
 
 
 def reorder_scratch_bytes(n, order, batch=128) -> int:

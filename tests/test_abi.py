@@ -22,7 +22,7 @@ def declared():
 
 def test_header_declares_the_boundary():
     names = declared()
-    for n in ("pcr_fb_bytes", "pcr_fb_clear", "pcr_render", "pcr_render_ex", "pcr_resolve",
+    for n in ("pcr_fb_bytes", "pcr_fb_clear", "pcr_render", "pcr_render_ex", "pcr_resolve", "pcr_resolve_depth",
               "pcr_reorder_scratch_bytes", "pcr_reorder", "pcr_batch_create", "pcr_batch_launch",
               "pcr_batch_destroy", "pcr_last_error", "pcr_version"):
         assert n in names
@@ -80,7 +80,35 @@ def test_render_rejects_bad_pointers_and_sizes():
     tune = pcr.Tune(4, 96, 0, 0, 0)
     assert L.pcr_render_ex(16, 10, m, 4, 4, 0, 16, ctypes.byref(tune), None) == pcr.EINVAL
     assert L.pcr_resolve(16, 4, 4, 0, None, None) == pcr.EINVAL
+    assert L.pcr_resolve_depth(16, 4, 4, 0, 0, 0.0, 0.0, 0.0, None, None, None) == pcr.EINVAL  # no depth_out
+    assert L.pcr_resolve_depth(16, 4, 4, 0, 2, 0.0, 0.0, 0.0, None, 16, None) == pcr.EINVAL    # mode
+    assert "mode" in L.pcr_last_error().decode()
+    assert L.pcr_resolve_depth(16, 4, 4, 0, 1, 0.0, 0.0, 0.0, 18, 16, None) == pcr.EINVAL      # rgba align
+    assert L.pcr_resolve_depth(16, 4, 4, 0, 1, 0.0, 0.0, 0.0, None, 18, None) == pcr.EINVAL    # depth align
+    assert L.pcr_resolve_depth(8, 4, 4, 0, 1, 0.0, 0.0, 0.0, None, 16, None) == pcr.EINVAL     # fb align
+    assert L.pcr_resolve_depth(16, 4, 4, 7, 1, 0.0, 0.0, 0.0, None, 16, None) == pcr.EINVAL    # variant
     assert L.pcr_fb_clear(None, 4, 4, 0, None) == pcr.EINVAL
+
+
+def test_chunk_argument_checks():
+    L = pcr.lib()
+    m = (ctypes.c_float * 16)()
+    assert L.pcr_chunks_scratch_bytes(0) == 0
+    assert L.pcr_chunks_scratch_bytes((1 << 24) + 1) == 0
+    assert L.pcr_chunks_scratch_bytes(1) == 256
+    assert L.pcr_chunks_scratch_bytes(100) == 1024
+    # nothing to draw: accepted without touching any pointer
+    assert L.pcr_render_chunks(None, 0, m, 4, 4, pcr.DEDUP, 16, None, 0, None, None) == pcr.OK
+    assert L.pcr_render_chunks(None, 3, m, 4, 4, pcr.DEDUP, 16, 256, 256, None, None) == pcr.EINVAL
+    assert L.pcr_render_chunks(16, 3, m, 4, 4, pcr.DEDUP, 16, None, 256, None, None) == pcr.EINVAL
+    assert L.pcr_render_chunks(16, 3, m, 4, 4, pcr.DEDUP, 16, 256, 16, None, None) == pcr.ENOMEM
+    assert L.pcr_render_chunks(16, 3, None, 4, 4, pcr.DEDUP, 16, 256, 256, None, None) == pcr.EINVAL
+    assert L.pcr_render_chunks(16, 3, m, 4, 4, pcr.DEDUP, 8, 256, 256, None, None) == pcr.EINVAL
+    assert L.pcr_render_chunks(16, (1 << 24) + 1, m, 4, 4, pcr.DEDUP, 16, 256, 1 << 30, None, None) == pcr.EINVAL
+    for v in (pcr.BASIC | pcr.F_EARLYZ, pcr.DEDUP | pcr.F_LDS, pcr.HQ | pcr.F_PLAIN, pcr.DEDUP | pcr.F_HQ_DEPTH):
+        assert L.pcr_render_chunks(16, 3, m, 4, 4, v, 16, 256, 256, None, None) in (pcr.EUNSUPPORTED, pcr.EINVAL)
+    assert L.pcr_render_chunks(16, 3, m, 4, 4, pcr.BASIC | pcr.F_EARLYZ, 16, 256, 256, None, None) == \
+        pcr.EUNSUPPORTED
 
 
 def test_reorder_argument_checks():

@@ -77,12 +77,13 @@ def test_empty_unused_and_capacity(orc, scene):
     plan.launch([])
     torch.cuda.synchronize()
     views = make_views(2, seed=3)
-    bufs = []
+    bufs, fbs = [], []
     pv = []
     for m, W, H, var in views:
         fb = pcr.alloc_fb(W, H, var)
         img = torch.zeros(W * H, dtype=torch.int32, device="cuda")
         bufs.append(img)
+        fbs.append(fb)          # the views hold raw pointers: keep the buffers alive
         pv.append(pcr.make_view(m, W, H, var, fb, img))
     pv[1].variant = -1          # unused slot: left untouched
     plan.launch(pv)

@@ -1,0 +1,166 @@
+"""GPU parity of many-chunk frames (one persistent launch over many separate
+point buffers) against the CPU oracle's frame of the same chunks, bit for bit."""
+import numpy as np
+import pytest
+
+from gpu_util import assert_same_fb, oracle_frame, read_fb, upload
+from paper_2104_07526_amd import pcr, synth
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [pcr.BASIC, pcr.DEDUP, pcr.HQ]
+SHAPES = [None, {"ppt": 1, "wg": 64}, {"ppt": 4, "wg": 1024}, {"ppt": 16, "wg": 256}, {"ppt": 8, "grid": 8},
+          {"ppt": 2, "wg": 128, "grid": 13}]
+
+
+def chunk_sizes(rng, n_chunks, mean):
+    """Chunk sizes of a level-of-detail octree: log-normal around `mean`, plus
+    the edge cases empty, 1 point and tile-sized +-1."""
+    s = np.maximum(1, rng.lognormal(np.log(mean), 0.8, n_chunks)).astype(np.int64)
+    edge = np.array([0, 1, 0, 255, 256, 257, 1023, 1024, 1025, 2047, 2048, 2049, 4095, 4097, 0])
+    return np.concatenate([edge, s])
+
+
+def split(pts, sizes, rng):
+    """Device copies of the chunks, in shuffled table order, some in their own
+    allocations and some as slices of one buffer.  Returns (buffers that must
+    stay alive, [(address, n)], the host points in table order)."""
+    import torch
+    total = int(sizes.sum())
+    assert total <= len(pts)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    whole = upload(pts[:total])
+    keep, table, host = [whole], [], []
+    for c in rng.permutation(len(sizes)):
+        a, b = int(offs[c]), int(offs[c + 1])
+        if c % 3 == 0 and b > a:
+            t = upload(pts[a:b])
+            keep.append(t)
+            addr = t.data_ptr()
+        else:
+            addr = whole.data_ptr() + 16 * a
+        table.append((addr, b - a))
+        host.append(pts[a:b])
+    torch.cuda.synchronize()
+    return keep, table, np.concatenate(host) if host else pts[:0]
+
+
+def chunk_frame(table_dev, nchunks, m, W, H, variant, tune=None):
+    import torch
+    fb = pcr.alloc_fb(W, H, variant)
+    pcr.fb_clear(fb, W, H, variant)
+    pcr.render_chunks(table_dev, nchunks, m, W, H, variant, fb, tune=tune)
+    img = pcr.resolve(fb, W, H, variant)
+    torch.cuda.synchronize()
+    return fb, img.cpu().numpy().view(np.uint32)
+
+
+@pytest.fixture(scope="module")
+def lod_scene():
+    """About 1.6M terrain points (shuffled Morton) in ~500 chunks of ~2.4k."""
+    import oracle
+    rng = np.random.default_rng(41)
+    pts = synth.terrain(1_700_000, seed=2)
+    pts = pts[oracle.default().reorder(pts, 1, 128, 3)]
+    sizes = chunk_sizes(rng, 480, 2400)
+    keep, table, host = split(pts, sizes, rng)
+    return keep, table, host
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("shape", range(len(SHAPES)))
+def test_lod_chunks_match_oracle(orc, lod_scene, variant, shape):
+    keep, table, host = lod_scene
+    W, H = 640, 360
+    m = synth.terrain_oblique(W, H)
+    efb, eimg = oracle_frame(orc, host, m, W, H, variant)
+    fb, img = chunk_frame(pcr.chunk_table(table), len(table), m, W, H, variant, SHAPES[shape])
+    assert_same_fb(read_fb(fb, W, H, variant), efb, variant)
+    assert np.array_equal(img, eimg)
+    assert np.count_nonzero(img) > 10_000
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_big_and_tiny_chunks(orc, variant):
+    """One chunk of 1M sphere points among 2000 chunks of 1-40 points."""
+    rng = np.random.default_rng(5)
+    pts = synth.sphere(1_060_000, seed=1)
+    sizes = np.concatenate([[1_000_000], rng.integers(1, 41, 2000)])
+    keep, table, host = split(pts, sizes, rng)
+    W, H = 1280, 720
+    m = synth.sphere_view(W, H)
+    efb, eimg = oracle_frame(orc, host, m, W, H, variant)
+    fb, img = chunk_frame(pcr.chunk_table(table), len(table), m, W, H, variant)
+    assert_same_fb(read_fb(fb, W, H, variant), efb, variant)
+    assert np.array_equal(img, eimg)
+
+
+def test_skipped_and_empty_chunks(orc):
+    """NULL, misaligned and oversized chunks contribute nothing; a table of
+    only empty chunks and nchunks = 0 leave the framebuffer cleared."""
+    import torch
+    rng = np.random.default_rng(6)
+    pts = synth.sphere(400_000, seed=3)
+    sizes = chunk_sizes(rng, 60, 3000)
+    keep, table, host = split(pts, sizes, rng)
+    base = keep[0].data_ptr()
+    bad = [(0, 1000), (base + 8, 500), (base, (1 << 36) + 1)]
+    mixed = table[:20] + bad[:1] + table[20:40] + bad[1:] + table[40:]
+    W, H = 320, 240
+    m = synth.sphere_view(W, H)
+    for variant in VARIANTS:
+        efb, eimg = oracle_frame(orc, host, m, W, H, variant)
+        fb, img = chunk_frame(pcr.chunk_table(mixed), len(mixed), m, W, H, variant)
+        assert_same_fb(read_fb(fb, W, H, variant), efb, variant)
+        assert np.array_equal(img, eimg)
+        for tab, cnt in ((pcr.chunk_table([(base, 0)] * 50), 50), (pcr.chunk_table([]), 0)):
+            fb, img = chunk_frame(tab, cnt, m, W, H, variant)
+            assert not img.any()
+            clear = pcr.alloc_fb(W, H, variant)
+            pcr.fb_clear(clear, W, H, variant)
+            torch.cuda.synchronize()
+            assert torch.equal(fb, clear)
+
+
+def test_hq_passes_split_and_accumulate(orc, lod_scene):
+    """HQ depth pass and colour pass as two calls, and a basic frame drawn
+    from two halves of the table into one framebuffer."""
+    import torch
+    keep, table, host = lod_scene
+    W, H = 512, 288
+    m = synth.terrain_oblique(W, H)
+    dev = pcr.chunk_table(table)
+    fb = pcr.alloc_fb(W, H, pcr.HQ)
+    pcr.fb_clear(fb, W, H, pcr.HQ)
+    pcr.render_chunks(dev, len(table), m, W, H, pcr.HQ | pcr.F_HQ_DEPTH, fb)
+    pcr.render_chunks(dev, len(table), m, W, H, pcr.HQ | pcr.F_HQ_COLOR, fb)
+    torch.cuda.synchronize()
+    efb, _ = oracle_frame(orc, host, m, W, H, pcr.HQ)
+    assert_same_fb(read_fb(fb, W, H, pcr.HQ), efb, pcr.HQ)
+    half = len(table) // 2
+    fb = pcr.alloc_fb(W, H, pcr.DEDUP)
+    pcr.fb_clear(fb, W, H, pcr.DEDUP)
+    pcr.render_chunks(pcr.chunk_table(table[:half]), half, m, W, H, pcr.DEDUP, fb)
+    pcr.render_chunks(pcr.chunk_table(table[half:]), len(table) - half, m, W, H, pcr.DEDUP, fb)
+    torch.cuda.synchronize()
+    efb, _ = oracle_frame(orc, host, m, W, H, pcr.DEDUP)
+    assert_same_fb(read_fb(fb, W, H, pcr.DEDUP), efb, pcr.DEDUP)
+
+
+def test_many_chunks_scan():
+    """20,000 chunks (more than one pass of the start-offset scan): the frame
+    equals the single-buffer render of the same points."""
+    import torch
+    rng = np.random.default_rng(7)
+    pts = synth.terrain(600_000, seed=9)
+    sizes = rng.integers(0, 50, 20_000)
+    keep, table, host = split(pts, sizes, rng)
+    W, H = 400, 300
+    m = synth.terrain_overview(W, H)
+    for variant in VARIANTS:
+        fb, img = chunk_frame(pcr.chunk_table(table), len(table), m, W, H, variant)
+        ref = pcr.alloc_fb(W, H, variant)
+        pcr.fb_clear(ref, W, H, variant)
+        pcr.render(upload(host), m, W, H, variant, ref)
+        torch.cuda.synchronize()
+        assert torch.equal(fb, ref)
