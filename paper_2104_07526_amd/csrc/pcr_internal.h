@@ -66,8 +66,8 @@ __device__ __forceinline__ Clip clip(const View &v, float x, float y, float z) {
 // more than 0.1% outside the view cone in clip space (the rounding of the
 // exact path is below 1e-6 relative).  NaN compares false: not certain.
 __device__ __forceinline__ bool surely_culled(const Clip &c) {
-    float lim = c.cw * 1.001f;
-    return c.cw <= 0.0f || c.cx > lim || c.cx < -lim || c.cy > lim || c.cy < -lim;
+    float lim = c.cw * 1.001f;  // >= 0 whenever the first test fails
+    return c.cw <= 0.0f || __builtin_fabsf(c.cx) > lim || __builtin_fabsf(c.cy) > lim;
 }
 
 // Correctly rounded 1/w: the hardware reciprocal estimate plus one FMA
@@ -95,7 +95,9 @@ __device__ __forceinline__ uint32_t finish(const View &v, const Clip &c, uint32_
     dbits = __float_as_uint(c.cw);
     uint32_t px = (uint32_t)(ok ? fx : 0.0f);
     uint32_t py = (uint32_t)(ok ? fy : 0.0f);
-    return ok ? py * v.W + px : kEmptyPid;
+    // py < H and W are below 2^24 and W*H below 2^32; __umul24 returns the
+    // low 32 bits of the product as a signed int, taken back as unsigned.
+    return ok ? (uint32_t)__umul24(py, v.W) + px : kEmptyPid;
 }
 
 __device__ __forceinline__ uint32_t project(const View &v, float x, float y, float z,

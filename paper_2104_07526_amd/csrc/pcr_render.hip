@@ -4,6 +4,10 @@
 // Data layout in HBM: points are a 16-byte array streamed once per geometry
 // pass with non-temporal 16-byte loads (one point per lane, 1 KiB per wave per
 // load); framebuffers are small (7-166 MB) and stay in L2 / Infinity Cache.
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "pcr_internal.h"
 
 namespace pcr {
@@ -197,12 +201,20 @@ struct Lds {
         shift = 32u - hbits;
     }
 
+    // Home slot: multiplicative hash on a 24-bit multiply (full rate; the
+    // tag keeps the whole pixel index, the hash only spreads the slots).
+    // __umul24 returns a signed int: shift it as unsigned, and mask, so the
+    // index can never leave the table.
+    __device__ __forceinline__ uint32_t home(uint32_t pid) const {
+        return ((uint32_t)__umul24(pid, 0x9E3779u) >> shift) & mask;
+    }
+
     // Slot of pixel `pid`, claimed if new (then appended to the list of the
     // tile with parity `par`), or kNoSlot when kMaxProbe slots in a row are
     // taken by other pixels -- the caller then updates the framebuffer
     // directly, which is always correct because min and + commute.
     __device__ __forceinline__ uint32_t slot(uint32_t pid, uint32_t par) {
-        uint32_t h = (pid * 0x9E3779B1u) >> shift;
+        uint32_t h = home(pid);
 #pragma unroll 1
         for (uint32_t probe = 0; probe < kMaxProbe; ++probe) {
             uint32_t t = __hip_atomic_load(tag + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -246,7 +258,7 @@ __device__ __forceinline__ bool dense_collapse(const Lds<V> &L, uint32_t pid, V 
         uint64_t m = __ballot(live && pid == p0);
         if (__popcll(m) < 24) break;
         act &= ~m;
-        uint32_t t0 = L.tag[(p0 * 0x9E3779B1u) >> L.shift];
+        uint32_t t0 = L.tag[L.home(p0)];
         if (t0 == p0) continue;  // slot exists: the early test filters
         bool in = (m >> lane) & 1ull;
         V mv = wave_min(in ? val : (V)~(V)0);
@@ -303,58 +315,106 @@ __device__ __forceinline__ void load_tile(const u32x4 *__restrict__ pts, uint64_
 }
 
 // Point sources of the render kernels.  FlatSrc: one contiguous buffer (the
-// kernel's `pts` argument).  ChunkSrc: the concatenation of many separate
-// buffers (level-of-detail chunks, Sec. 5.4); the tiles run over the virtual
-// concatenation, so small chunks share tiles and no lane idles at a chunk's
-// end.  start[c] is the first virtual index of chunk c, start[nchunks] the
-// total; both are written on the device by k_chunk_starts, so the tile count
-// is only known inside the kernel (setup()).
+// kernel's `pts` argument), one tile per workgroup.  ChunkSrc: the
+// concatenation of many separate buffers (level-of-detail chunks, Sec. 5.4);
+// tiles run over the virtual concatenation, so small chunks share tiles and no
+// lane idles at a chunk's end.  start[c] is the first virtual index of chunk c
+// and start[nchunks] the total, written on the device by k_chunk_starts, so
+// the tile count is only known inside the kernel (setup()).
 struct FlatSrc {
     static constexpr bool chunked = false;
-    __device__ __forceinline__ void setup(Tiles &, uint32_t) const {}
+    __device__ __forceinline__ void setup(Tiles &, uint32_t) {}
+    __device__ __forceinline__ bool tile(const Tiles &tl, uint64_t b, uint64_t &t) { return tl.tile(b, t); }
     template <int PPT>
     __device__ __forceinline__ void load(const u32x4 *__restrict__ pts, uint64_t first, uint32_t wg, uint64_t n,
-                                         u32x4 (&p)[PPT]) const {
+                                         u32x4 (&p)[PPT]) {
         load_tile<PPT>(pts, first, wg, n, p);
     }
 };
 
 struct ChunkSrc {
     static constexpr bool chunked = true;
+    static constexpr int K = 4;  // chunks a tile may span on the fast path
     const pcr_chunk *chunks;
     const uint64_t *start;
     uint32_t nchunks;
+    // Per workgroup (set up in the kernel): the contiguous tile range
+    // [t_next, t_end) and the chunk holding the next tile's first point.
+    uint64_t t_next, t_end;
+    uint32_t cur;
 
-    // Every workgroup takes tiles b, b + grid, ... (grid a multiple of 8, so
-    // a workgroup stays on one XCD) through the XCD-contiguous tile mapping.
-    __device__ __forceinline__ void setup(Tiles &tl, uint32_t T) const {
-        const uint64_t n = start[nchunks];
-        tl.n = n;
-        tl.ntiles = (n + T - 1) / T;
-        tl.nblocks = (tl.ntiles + 7) / 8 * 8;
-        tl.remap = 1;
-    }
-    template <int PPT>
-    __device__ __forceinline__ void load(const u32x4 *__restrict__, uint64_t first, uint32_t wg, uint64_t n,
-                                         u32x4 (&p)[PPT]) const {
-        // Chunk of the tile's first point: the last c with start[c] <= first
-        // (uniform binary search; start[nchunks] = n > first).
+    // Last c with start[c] <= g (start[0] = 0 <= g < start[nchunks]).
+    __device__ __forceinline__ uint32_t find(uint64_t g) const {
         uint32_t lo = 0, hi = nchunks;
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) / 2;
-            if (start[mid] <= first) lo = mid;
+            if (start[mid] <= g) lo = mid;
             else hi = mid;
         }
-        // Each lane walks forward to the chunk of its own points (indices
-        // grow with j; lanes past the end take the last point, discarded by
-        // the caller).
-        uint32_t c = lo;
+        return lo;
+    }
+
+    // Static XCD-aware schedule: workgroups are dispatched round-robin over
+    // the 8 XCDs; the workgroups of XCD x split the x-th eighth of the tiles
+    // into contiguous ranges, so a workgroup's tiles follow each other and its
+    // chunk cursor only moves forward (no search per tile).
+    __device__ __forceinline__ void setup(Tiles &tl, uint32_t T) {
+        const uint64_t n = start[nchunks];
+        tl.n = n;
+        tl.ntiles = (n + T - 1) / T;
+        const uint32_t nx = gridDim.x < 8u ? gridDim.x : 8u;
+        const uint32_t xcd = blockIdx.x % nx, lane_wg = blockIdx.x / nx;
+        const uint32_t wgs_x = (gridDim.x - xcd + nx - 1u) / nx;
+        const uint64_t per_x = (tl.ntiles + nx - 1) / nx;
+        const uint64_t x_lo = xcd * per_x < tl.ntiles ? xcd * per_x : tl.ntiles;
+        const uint64_t x_hi = x_lo + per_x < tl.ntiles ? x_lo + per_x : tl.ntiles;
+        const uint64_t per_wg = (x_hi - x_lo + wgs_x - 1) / wgs_x;
+        const uint64_t lo = x_lo + lane_wg * per_wg;
+        t_next = lo < x_hi ? lo : x_hi;
+        t_end = t_next + per_wg < x_hi ? t_next + per_wg : x_hi;
+        tl.nblocks = blockIdx.x + (t_end - t_next) * gridDim.x;  // this workgroup's loop count
+        cur = t_next < t_end ? find(t_next * T) : 0u;
+    }
+    __device__ __forceinline__ bool tile(const Tiles &, uint64_t, uint64_t &t) {
+        t = t_next++;
+        return true;
+    }
+    template <int PPT>
+    __device__ __forceinline__ void load(const u32x4 *__restrict__, uint64_t first, uint32_t wg, uint64_t n,
+                                         u32x4 (&p)[PPT]) {
+        while (start[cur + 1] <= first) ++cur;  // uniform, usually 0 or 1 step
+        // Window of the next K chunks: their starts and buffers, uniform.
+        uint64_t s[K + 1];
+        const u32x4 *b[K];
+#pragma unroll
+        for (int k = 0; k <= K; ++k) s[k] = start[cur + k < nchunks ? cur + k : nchunks];
+#pragma unroll
+        for (int k = 0; k < K; ++k) b[k] = (const u32x4 *)chunks[cur + k < nchunks ? cur + k : nchunks - 1].pts;
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             uint64_t g = first + (uint64_t)(j * wg + threadIdx.x);
-            if (g >= n) g = n - 1;
-            while (start[c + 1] <= g) ++c;
-            p[j] = load_point((const u32x4 *)chunks[c].pts + (g - start[c]));
+            if (g >= n) g = n - 1;  // lanes past the end: discarded by the caller
+            // Chunk offset in the window: boundaries passed (empty chunks
+            // have equal starts and are passed together with their successor).
+            uint32_t k = 0;
+#pragma unroll
+            for (int q = 1; q <= K; ++q) k += g >= s[q] ? 1u : 0u;
+            const u32x4 *base = b[0];
+            uint64_t sb = s[0];
+#pragma unroll
+            for (int q = 1; q < K; ++q) {
+                base = k == (uint32_t)q ? b[q] : base;
+                sb = k == (uint32_t)q ? s[q] : sb;
+            }
+            if (k == (uint32_t)K) {  // more than K chunks in this tile: walk
+                uint32_t c = cur + K;
+                while (start[c + 1] <= g) ++c;
+                base = (const u32x4 *)chunks[c].pts;
+                sb = start[c];
+            }
+            // The buffer addresses come from memory, so name the global
+            // address space (a generic load would also wait on LDS traffic).
+            p[j] = __builtin_nontemporal_load((const __attribute__((address_space(1))) u32x4 *)(base + (g - sb)));
         }
     }
 };
@@ -368,7 +428,7 @@ __global__ __launch_bounds__(1024) void k_basic(const u32x4 *__restrict__ pts, T
     if constexpr (Src::chunked) src.setup(tl, wg * PPT);
     for (uint64_t b = blockIdx.x; b < tl.nblocks; b += gridDim.x) {
         uint64_t t;
-        if (!tl.tile(b, t)) continue;
+        if (!src.tile(tl, b, t)) continue;
         const uint64_t first = t * wg * PPT;
         const uint64_t base = first + threadIdx.x;
         u32x4 p[PPT];
@@ -414,7 +474,7 @@ __global__ __launch_bounds__(1024) void k_dedup(const u32x4 *__restrict__ pts, T
     uint32_t par = 0;
     for (uint64_t b = blockIdx.x; b < tl.nblocks; b += gridDim.x) {
         uint64_t t;
-        if (!tl.tile(b, t)) continue;
+        if (!src.tile(tl, b, t)) continue;
         const uint64_t first = t * wg * PPT;
         const uint64_t base = first + threadIdx.x;
         u32x4 p[PPT];
@@ -506,7 +566,7 @@ __global__ __launch_bounds__(1024) void k_hq_color(const u32x4 *__restrict__ pts
     uint32_t par = 0;
     for (uint64_t b = blockIdx.x; b < tl.nblocks; b += gridDim.x) {
         uint64_t t;
-        if (!tl.tile(b, t)) continue;
+        if (!src.tile(tl, b, t)) continue;
         const uint64_t first = t * wg * PPT;
         const uint64_t base = first + threadIdx.x;
         u32x4 p[PPT];
@@ -808,12 +868,23 @@ __global__ __launch_bounds__(1024) void k_chunk_starts(const pcr_chunk *__restri
 }
 
 // Workgroups resident at once (a multiple of 8), unless the caller fixed it.
+// The occupancy query is made once per device, kernel and launch shape.
 uint32_t persistent_grid(const void *fn, uint32_t wg, size_t sm, uint32_t want) {
     if (want) return want;
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void *, uint32_t, size_t>, uint32_t> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const auto key = std::make_tuple(dev, fn, wg, sm);
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
     int per = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, (int)wg, sm) != hipSuccess || per < 1) per = 1;
-    uint32_t g = (uint32_t)per * (uint32_t)device_cus() / 8u * 8u;
-    return g < 8u ? 8u : g;
+    uint32_t grid = (uint32_t)per * (uint32_t)device_cus() / 8u * 8u;
+    if (grid < 8u) grid = 8u;
+    cache.emplace(key, grid);
+    return grid;
 }
 
 struct ChunkLaunch {
