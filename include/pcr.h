@@ -114,7 +114,8 @@ enum {
  *   ppt    points per thread (1, 2, 4, 8 or 16)
  *   wg     workgroup size (64, 128, 256, 512 or 1024)
  *   grid   workgroups per launch (0 = one tile of wg*ppt points per workgroup)
- *   group  views per point pass in a batch (0 = all that fit the cache budget)
+ *   group  views per point pass in a batch (0 = all that fit the cache budget;
+ *          1 = every view its own pass with the single-view kernels)
  *   slots  LDS hash-table slots per workgroup of the deduplicating kernels,
  *          rounded up to a power of two in [256, 32768] (0 = half a tile) */
 typedef struct pcr_tune {
@@ -257,7 +258,8 @@ typedef struct pcr_view {
 
 /* A batch plan renders up to `capacity` views of one resident point buffer per
  * launch: the framebuffers are cleared, every view's points are rendered in
- * persistent kernels that load each point once per group of views, and every
+ * persistent kernels that load each point once per group of views (or, with
+ * tune->group == 1, by one single-view render pass per view slot), and every
  * view is resolved.  The launch is a single hipGraph replay.  Each view's
  * image is bit-identical to pcr_fb_clear + pcr_render + pcr_resolve of that
  * view alone.  The plan allocates its device view table and graph at

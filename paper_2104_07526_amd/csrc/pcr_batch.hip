@@ -14,6 +14,7 @@
 // the point stream is read once per group.  Every update is an integer min or
 // sum, so each view is bit-identical to rendering it alone.
 #include <algorithm>
+#include <cstddef>
 #include <cstring>
 #include <vector>
 
@@ -25,15 +26,7 @@ namespace {
 constexpr uint32_t kBatchWg = 256;
 constexpr uint64_t kGroupBudget = 160ull << 20;  // framebuffer bytes per group
 
-struct DevView {
-    View v;
-    int32_t variant;  // PCR_BASIC / PCR_DEDUP / PCR_HQ
-    uint32_t pad;
-    u64 *fb;          // basic key buffer
-    uint32_t *D;      // HQ depth
-    u64 *S;           // HQ sums
-    uint32_t *out;
-};
+using DevView = BatchView;
 
 struct Group {
     uint32_t first, count;  // range of the pass's view-index list
@@ -158,8 +151,15 @@ struct BLds {
         mask = (1u << hbits) - 1u;
         shift = 32u - hbits;
     }
+    // Home slot of a (view slot, pixel) tag: the view bits are folded into
+    // the low 24 bits, then a full-rate 24-bit multiplicative hash (__umul24
+    // returns a signed int: shifted as unsigned and masked into the table).
+    __device__ __forceinline__ uint32_t home(uint32_t key) const {
+        const uint32_t k = (key ^ (key >> 20)) & 0xFFFFFFu;
+        return ((uint32_t)__umul24(k, 0x9E3779u) >> shift) & mask;
+    }
     __device__ __forceinline__ uint32_t slot(uint32_t pid) {
-        uint32_t h = (pid * 0x9E3779B1u) >> shift;
+        uint32_t h = home(pid);
 #pragma unroll 1
         for (uint32_t probe = 0; probe < kMaxProbeB; ++probe) {
             uint32_t t = __hip_atomic_load(tag + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -374,6 +374,11 @@ struct pcr_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint32_t grid_pass[2] = {0, 0}, grid_io = 0;
+    // Per-view mode: the graph node of each (pass, slot) and whether it is
+    // enabled in `exec`; slots a launch does not use are disabled, so they
+    // cost no dispatch.
+    std::vector<hipGraphNode_t> vnode[2];
+    std::vector<uint8_t> von[2];
 };
 
 namespace pcr {
@@ -417,11 +422,48 @@ int launch_pass(pcr_batch *b, int pass, hipStream_t s) {
     return PCR_OK;
 }
 
+// Per-view mode (group 1): every view slot gets the single-view passes; a
+// slot beyond the launch's view count ends at once.
+int view_passes(pcr_batch *b, int pass, hipStream_t s) {
+    const BatchView *views = (const BatchView *)(b->dtable + b->lay.views);
+    const uint32_t *nv = (const uint32_t *)(b->dtable + offsetof(Header, nviews));
+    if (pass < 0) return launch_view_pass(-1, b->pts, b->n, views, nv, 0, b->sh, s);
+    b->vnode[pass].assign(b->capacity, nullptr);
+    b->von[pass].assign(b->capacity, 1);
+    for (uint32_t i = 0; i < b->capacity; ++i) {
+        if (int rc = launch_view_pass(pass, b->pts, b->n, views, nv, i, b->sh, s)) return rc;
+        // The kernel just captured is the stream's only dependency now.
+        hipStreamCaptureStatus st;
+        const hipGraphNode_t *deps = nullptr;
+        size_t ndeps = 0;
+        if (hipStreamGetCaptureInfo_v2(s, &st, nullptr, nullptr, &deps, &ndeps) != hipSuccess ||
+            st != hipStreamCaptureStatusActive || ndeps != 1)
+            return fail(PCR_EHIP, "could not identify the captured node of view slot %u", i);
+        b->vnode[pass][i] = deps[0];
+    }
+    return PCR_OK;
+}
+
+// Enables the per-view nodes the launch needs (slot i < nviews; the colour
+// pass only for HQ views) and disables the others.
+int select_view_nodes(pcr_batch *b, const std::vector<BatchView> &dv) {
+    for (int pass = 0; pass < 2; ++pass) {
+        for (uint32_t i = 0; i < b->capacity; ++i) {
+            const uint8_t want = i < dv.size() && (pass == 0 || dv[i].variant == PCR_HQ);
+            if (b->von[pass][i] == want) continue;
+            PCR_HIP(hipGraphNodeSetEnabled(b->exec, b->vnode[pass][i], want));
+            b->von[pass][i] = want;
+        }
+    }
+    return PCR_OK;
+}
+
 int record(pcr_batch *b, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_clear, dim3(b->grid_io), dim3(256), 0, s, b->dtable, b->lay);
     PCR_LAUNCHED();
-    int rc = launch_pass(b, 0, s);
-    if (rc == PCR_OK) rc = launch_pass(b, 1, s);
+    const bool per_view = b->sh.group == 1;
+    int rc = per_view ? view_passes(b, 0, s) : launch_pass(b, 0, s);
+    if (rc == PCR_OK) rc = per_view ? view_passes(b, 1, s) : launch_pass(b, 1, s);
     if (rc != PCR_OK) return rc;
     hipLaunchKernelGGL(k_batch_resolve, dim3(b->grid_io), dim3(256), 0, s, b->dtable, b->lay);
     PCR_LAUNCHED();
@@ -501,6 +543,7 @@ extern "C" int pcr_batch_create(pcr_batch **plan, const pcr_point *pts, uint64_t
         return fail(PCR_EHIP, "plan set-up failed");
     }
     rc = launch_pass(b, -1, nullptr);
+    if (rc == PCR_OK && b->sh.group == 1) rc = view_passes(b, -1, nullptr);
     if (rc != PCR_OK) {
         destroy(b);
         return rc;
@@ -583,6 +626,8 @@ extern "C" int pcr_batch_launch(pcr_batch *b, const pcr_view *views, uint32_t nv
         }
         h->ngroups[pass] = ng;
     }
+    if (B.sh.group == 1)
+        if (int rc = select_view_nodes(b, dv)) return rc;
     hipStream_t s = (hipStream_t)stream;
     PCR_HIP(hipMemcpyAsync(B.dtable, st, B.lay.bytes, hipMemcpyHostToDevice, s));
     PCR_HIP(hipGraphLaunch(B.exec, s));

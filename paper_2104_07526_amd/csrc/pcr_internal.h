@@ -190,4 +190,23 @@ int resolve_shape(const pcr_tune *tune, int family, Shape &s);
 // Kernels launched by more than one translation unit.
 int launch_fill(void *p, size_t bytes, uint32_t word, hipStream_t s);
 
+// One view slot of a batch plan's device table.
+struct BatchView {
+    View v;
+    int32_t variant;  // PCR_BASIC / PCR_DEDUP / PCR_HQ
+    uint32_t pad;
+    u64 *fb;          // basic key buffer
+    uint32_t *D;      // HQ depth
+    u64 *S;           // HQ sums
+    uint32_t *out;
+};
+
+// Single-view render pass of batch slot `slot`, read from a plan's device
+// table when the kernel runs (nothing happens if slot >= *nviews): pass 0 the
+// closest-point render or the HQ depth pass, pass 1 the HQ colour pass, each
+// with the single-view deduplicating kernels.  pass < 0 only raises the
+// kernels' LDS limits (to be done before a graph capture).
+int launch_view_pass(int pass, const u32x4 *pts, uint64_t n, const BatchView *views, const uint32_t *nviews,
+                     uint32_t slot, const Shape &sh, hipStream_t s);
+
 }  // namespace pcr

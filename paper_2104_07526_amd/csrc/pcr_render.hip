@@ -458,8 +458,8 @@ __device__ __forceinline__ void direct_min(V *fb, uint32_t pid, V val, bool earl
 }
 
 template <typename V, int PPT, bool EARLYZ, bool REDUCE, class Src>
-__global__ __launch_bounds__(1024) void k_dedup(const u32x4 *__restrict__ pts, Tiles tl, View v,
-                                                V *__restrict__ fb, uint32_t hbits, Src src) {
+__device__ __forceinline__ void dedup_tiles(const u32x4 *__restrict__ pts, Tiles tl, const View &v,
+                                            V *__restrict__ fb, uint32_t hbits, Src src) {
     extern __shared__ __align__(16) unsigned char smem[];
     Lds<V> L(smem, hbits);
     const uint32_t wg = blockDim.x;
@@ -520,6 +520,12 @@ __global__ __launch_bounds__(1024) void k_dedup(const u32x4 *__restrict__ pts, T
     }
 }
 
+template <typename V, int PPT, bool EARLYZ, bool REDUCE, class Src>
+__global__ __launch_bounds__(1024) void k_dedup(const u32x4 *__restrict__ pts, Tiles tl, View v,
+                                                V *__restrict__ fb, uint32_t hbits, Src src) {
+    dedup_tiles<V, PPT, EARLYZ, REDUCE, Src>(pts, tl, v, fb, hbits, src);
+}
+
 // HQ depth pass without LDS (Sec. 3.5: a 32-bit atomicMin of the depth).
 template <int PPT, bool EARLYZ>
 __global__ __launch_bounds__(1024) void k_hq_depth(const u32x4 *__restrict__ pts, Tiles tl, View v,
@@ -547,9 +553,9 @@ __global__ __launch_bounds__(1024) void k_hq_depth(const u32x4 *__restrict__ pts
 // (depth <= fl32(closest * 1.01f)) adds (r << 32 | g) and (b << 32 | 1) to the
 // pixel's two 64-bit sums.
 template <int PPT, bool LDS, class Src>
-__global__ __launch_bounds__(1024) void k_hq_color(const u32x4 *__restrict__ pts, Tiles tl, View v,
-                                                   const uint32_t *__restrict__ D,
-                                                   u64 *__restrict__ S, uint32_t hbits, Src src) {
+__device__ __forceinline__ void hq_color_tiles(const u32x4 *__restrict__ pts, Tiles tl, const View &v,
+                                               const uint32_t *__restrict__ D, u64 *__restrict__ S,
+                                               uint32_t hbits, Src src) {
     extern __shared__ __align__(16) unsigned char smem[];
     const uint32_t wg = blockDim.x;
     if constexpr (Src::chunked) src.setup(tl, wg * PPT);
@@ -616,6 +622,45 @@ __global__ __launch_bounds__(1024) void k_hq_color(const u32x4 *__restrict__ pts
         }
         lds_barrier();
         par ^= 1u;
+    }
+}
+
+template <int PPT, bool LDS, class Src>
+__global__ __launch_bounds__(1024) void k_hq_color(const u32x4 *__restrict__ pts, Tiles tl, View v,
+                                                   const uint32_t *__restrict__ D,
+                                                   u64 *__restrict__ S, uint32_t hbits, Src src) {
+    hq_color_tiles<PPT, LDS, Src>(pts, tl, v, D, S, hbits, src);
+}
+
+// Single-view passes driven by a batch plan's table: the view is read on the
+// device (so a captured graph serves any views), its words moved to scalar
+// registers like the arguments of the single-view kernels.
+__device__ __forceinline__ View uniform_view(const View *p) {
+    View v;
+    const uint32_t *src = (const uint32_t *)p;
+    uint32_t *dst = (uint32_t *)&v;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(View) / 4); ++i) dst[i] = (uint32_t)__builtin_amdgcn_readfirstlane((int)src[i]);
+    return v;
+}
+
+template <int PPT, int PASS>
+__global__ __launch_bounds__(1024) void k_view_pass(const u32x4 *__restrict__ pts, Tiles tl,
+                                                    const BatchView *__restrict__ views,
+                                                    const uint32_t *__restrict__ nviews, uint32_t slot,
+                                                    uint32_t hbits) {
+    if (slot >= *nviews) return;
+    const BatchView *bv = views + slot;
+    const int variant = __builtin_amdgcn_readfirstlane(bv->variant);
+    if (PASS == 1 && variant != PCR_HQ) return;
+    const View v = uniform_view(&bv->v);
+    if (PASS == 0) {
+        if (variant == PCR_HQ)
+            dedup_tiles<uint32_t, PPT, false, true, FlatSrc>(pts, tl, v, bv->D, hbits, FlatSrc{});
+        else
+            dedup_tiles<u64, PPT, false, true, FlatSrc>(pts, tl, v, bv->fb, hbits, FlatSrc{});
+    } else {
+        hq_color_tiles<PPT, true, FlatSrc>(pts, tl, v, bv->D, bv->S, hbits, FlatSrc{});
     }
 }
 
@@ -945,11 +990,37 @@ struct ChunkL {
     }
 };
 
+template <int P>
+struct ViewL {
+    static int run(int pass, const u32x4 *pts, uint64_t n, const BatchView *views, const uint32_t *nviews,
+                   uint32_t slot, const Shape &sh, hipStream_t s) {
+        const uint32_t T = sh.wg * P, hb = lds_hbits(T, sh.slots);
+        const size_t sm0 = lds_bytes(hb, 8), sm1 = lds_bytes(hb, 16);
+        if (sm1 > max_lds()) return fail(PCR_EINVAL, "tile of %u points needs %zu bytes of LDS", T, sm1);
+        if (pass < 0) {
+            int rc = allow_lds((const void *)&k_view_pass<P, 0>, sm0);
+            return rc ? rc : allow_lds((const void *)&k_view_pass<P, 1>, sm1);
+        }
+        uint32_t grid;
+        const Tiles tl = make_tiles(n, sh, grid);
+        if (pass == 0)
+            hipLaunchKernelGGL((k_view_pass<P, 0>), dim3(grid), dim3(sh.wg), sm0, s, pts, tl, views, nviews, slot, hb);
+        else
+            hipLaunchKernelGGL((k_view_pass<P, 1>), dim3(grid), dim3(sh.wg), sm1, s, pts, tl, views, nviews, slot, hb);
+        PCR_LAUNCHED();
+        return PCR_OK;
+    }
+};
+
 }  // namespace
 
 int render_basic(const Launch &L) { return by_ppt<BasicL>(L.sh.ppt, L); }
 int render_hq_depth(const Launch &L) { return by_ppt<DepthL>(L.sh.ppt, L); }
 int render_hq_color(const Launch &L, uint32_t w, uint32_t h) { return by_ppt<ColorL>(L.sh.ppt, L, w, h); }
+int launch_view_pass(int pass, const u32x4 *pts, uint64_t n, const BatchView *views, const uint32_t *nviews,
+                     uint32_t slot, const Shape &sh, hipStream_t s) {
+    return by_ppt<ViewL>(sh.ppt, pass, pts, n, views, nviews, slot, sh, s);
+}
 
 }  // namespace pcr
 

@@ -18,7 +18,8 @@ from . import pcr
 CACHE = os.environ.get("PCR_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "pcr_tune.json"))
 _lock = threading.Lock()
 
-BATCH_CANDIDATES = [{"ppt": p, "group": g} for p in (4, 8) for g in (4, 8, 16, 32)]
+# group 1: each view its own single-view pass inside the plan's graph
+BATCH_CANDIDATES = [{"ppt": p, "group": g} for p in (4, 8) for g in (1, 4, 8, 16, 32)]
 RENDER_CANDIDATES = [{"ppt": p, "wg": w, "slots": s} for p in (4, 8, 16) for w in (256, 512)
                      for s in (0, 1024, 2048)]
 

@@ -40,7 +40,8 @@ def scene():
     return pts, upload(pts)
 
 
-@pytest.mark.parametrize("tune", [None, {"ppt": 4}, {"ppt": 8, "group": 2}, {"ppt": 16, "slots": 256}])
+@pytest.mark.parametrize("tune", [None, {"ppt": 4}, {"ppt": 8, "group": 2}, {"ppt": 16, "slots": 256},
+                                  {"ppt": 8, "group": 1}, {"ppt": 2, "group": 1, "slots": 256}])
 def test_views_match_oracle(orc, scene, tune):
     pts, d = scene
     views = make_views(9, seed=11)
@@ -53,11 +54,12 @@ def test_views_match_oracle(orc, scene, tune):
     plan.close()
 
 
-def test_replays_with_eager_work_between(orc, scene):
+@pytest.mark.parametrize("tune", [None, {"group": 1}])
+def test_replays_with_eager_work_between(orc, scene, tune):
     """The graph is replayed with new views each time; eager single-view
     renders run between the replays; every replay is checked."""
     pts, d = scene
-    plan = pcr.BatchPlan(d, capacity=6)
+    plan = pcr.BatchPlan(d, capacity=6, tune=tune)
     for rep in range(4):
         views = make_views(5 + rep % 2, seed=100 + rep)
         bufs = run_batch(plan, views)
@@ -137,3 +139,30 @@ def test_many_views_fill_the_shared_table(orc):
                 assert np.array_equal(img.cpu().numpy().view(np.uint32), eimg)
         plan.close()
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("tune", [None, {"group": 1}])
+def test_back_to_back_launches_of_varying_size(orc, scene, tune):
+    """Launches of 8, 2, 5, 1 and 8 views enqueued back to back on one stream
+    without waiting (per-view plans enable only the slots each launch uses);
+    every image of every launch equals the oracle."""
+    import torch
+    pts, d = scene
+    plan = pcr.BatchPlan(d, capacity=8, tune=tune)
+    launches = []
+    for k, cnt in enumerate((8, 2, 5, 1, 8)):
+        views = make_views(cnt, seed=300 + k)
+        bufs, pv = [], []
+        for m, W, H, var in views:
+            fb = pcr.alloc_fb(W, H, var)
+            img = torch.zeros(W * H, dtype=torch.int32, device="cuda")
+            bufs.append((fb, img))
+            pv.append(pcr.make_view(m, W, H, var, fb, img))
+        plan.launch(pv)
+        launches.append((views, bufs))
+    torch.cuda.synchronize()
+    for k, (views, bufs) in enumerate(launches):
+        for (m, W, H, var), (fb, img) in zip(views, bufs):
+            _, eimg = oracle_frame(orc, pts, m, W, H, var)
+            assert np.array_equal(img.cpu().numpy().view(np.uint32), eimg), (k, var)
+    plan.close()
