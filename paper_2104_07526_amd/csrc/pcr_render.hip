@@ -38,69 +38,55 @@ int launch_fill(void *p, size_t bytes, uint32_t word, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Wavefront reduction of Sec. 3.3 on a 64-lane wavefront: when every live lane
-// targets one pixel, only the lanes holding the wave's minimum write (first
-// listing); otherwise neighbouring lane pairs merge (second listing).  Keys are
-// compared whole, so a lane that loses can never hold the pixel's minimum.
+// Wavefront reduction of Sec. 3.3 on a 64-lane wavefront: when many live lanes
+// target one pixel, only the lanes holding the group's smallest depth go on
+// (first listing); otherwise neighbouring lane pairs merge (second listing).
+// A lane that drops out can never hold the pixel's minimum key.
 // ---------------------------------------------------------------------------
-// Wave-wide reductions with DPP moves (VALU, no LDS traffic): pairs, quads,
-// half rows and rows by quad_perm / row mirrors, then rows combined by
-// row_bcast:15 and row_bcast:31; lane 63 ends with the total.  Lanes outside
-// a DPP pattern's row mask keep the identity.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ u64 dpp64(u64 x, u64 ident) {
-    uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)ident, (int)(uint32_t)x, CTRL, ROWS, 0xF, false);
-    uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(ident >> 32), (int)(uint32_t)(x >> 32), CTRL,
-                                                        ROWS, 0xF, false);
-    return ((u64)hi << 32) | lo;
-}
-
+// Wave-wide reductions with DPP moves (VALU, no LDS traffic), 32 bits wide:
+// pairs, quads, half rows and rows by quad_perm / row mirrors, then rows
+// combined by row_bcast:15 and row_bcast:31; lane 63 ends with the total.
+// Lanes outside a DPP pattern's row mask keep the identity.
 template <int CTRL, int ROWS>
 __device__ __forceinline__ uint32_t dpp32(uint32_t x, uint32_t ident) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)ident, (int)x, CTRL, ROWS, 0xF, false);
 }
 
-__device__ __forceinline__ u64 vmin(u64 a, u64 b) { return b < a ? b : a; }
 __device__ __forceinline__ uint32_t vmin(uint32_t a, uint32_t b) { return b < a ? b : a; }
 
-__device__ __forceinline__ u64 readlane64(u64 x, uint32_t lane) {
-    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, lane);
-    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), lane);
-    return ((u64)hi << 32) | lo;
-}
-
 // Minimum over the wavefront (uniform result).
-__device__ __forceinline__ u64 wave_min(u64 x) {
-    const u64 I = ~0ull;
-    x = vmin(x, dpp64<0xB1, 0xF>(x, I));   // quad_perm [1,0,3,2]
-    x = vmin(x, dpp64<0x4E, 0xF>(x, I));   // quad_perm [2,3,0,1]
-    x = vmin(x, dpp64<0x141, 0xF>(x, I));  // row_half_mirror
-    x = vmin(x, dpp64<0x140, 0xF>(x, I));  // row_mirror
-    x = vmin(x, dpp64<0x142, 0xA>(x, I));  // row_bcast:15
-    x = vmin(x, dpp64<0x143, 0xC>(x, I));  // row_bcast:31
-    return readlane64(x, 63);
-}
-
 __device__ __forceinline__ uint32_t wave_min(uint32_t x) {
     const uint32_t I = ~0u;
-    x = vmin(x, dpp32<0xB1, 0xF>(x, I));
-    x = vmin(x, dpp32<0x4E, 0xF>(x, I));
-    x = vmin(x, dpp32<0x141, 0xF>(x, I));
-    x = vmin(x, dpp32<0x140, 0xF>(x, I));
-    x = vmin(x, dpp32<0x142, 0xA>(x, I));
-    x = vmin(x, dpp32<0x143, 0xC>(x, I));
+    x = vmin(x, dpp32<0xB1, 0xF>(x, I));   // quad_perm [1,0,3,2]
+    x = vmin(x, dpp32<0x4E, 0xF>(x, I));   // quad_perm [2,3,0,1]
+    x = vmin(x, dpp32<0x141, 0xF>(x, I));  // row_half_mirror
+    x = vmin(x, dpp32<0x140, 0xF>(x, I));  // row_mirror
+    x = vmin(x, dpp32<0x142, 0xA>(x, I));  // row_bcast:15
+    x = vmin(x, dpp32<0x143, 0xC>(x, I));  // row_bcast:31
     return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
-// Sum over the wavefront (uniform result), modulo 2^64.
-__device__ __forceinline__ u64 wave_sum(u64 x) {
-    x += dpp64<0xB1, 0xF>(x, 0ull);
-    x += dpp64<0x4E, 0xF>(x, 0ull);
-    x += dpp64<0x141, 0xF>(x, 0ull);
-    x += dpp64<0x140, 0xF>(x, 0ull);
-    x += dpp64<0x142, 0xA>(x, 0ull);
-    x += dpp64<0x143, 0xC>(x, 0ull);
-    return readlane64(x, 63);
+// Sum over the wavefront (uniform result), modulo 2^32.
+__device__ __forceinline__ uint32_t wave_sum(uint32_t x) {
+    x += dpp32<0xB1, 0xF>(x, 0u);
+    x += dpp32<0x4E, 0xF>(x, 0u);
+    x += dpp32<0x141, 0xF>(x, 0u);
+    x += dpp32<0x140, 0xF>(x, 0u);
+    x += dpp32<0x142, 0xA>(x, 0u);
+    x += dpp32<0x143, 0xC>(x, 0u);
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+// Depth bits of a value: the high word of a 64-bit key, or the value itself
+// (HQ depth pass).  The key with the smallest depth bits is among the keys
+// whose depth equals the minimum, so a group can keep just those lanes
+// (a 32-bit reduction) and leave the colour tie-break to the atomic minimum.
+template <typename V>
+__device__ __forceinline__ uint32_t depth_of(V val) {
+    if constexpr (sizeof(V) == 8)
+        return (uint32_t)(val >> 32);
+    else
+        return (uint32_t)val;
 }
 
 template <typename V>
@@ -130,8 +116,8 @@ __device__ __forceinline__ bool wave_reduce(uint32_t pid, V val, bool live) {
         uint64_t m = __ballot(live && pid == p0);
         if (__popcll(m) < 24) break;
         bool in = (m >> lane) & 1ull;
-        V mv = wave_min(in ? val : (V)~(V)0);
-        if (in) live = val == mv;  // equal keys may all write: harmless
+        const uint32_t md = wave_min(in ? depth_of(val) : ~0u);
+        if (in) live = depth_of(val) == md;  // the group's minimum is among these lanes
         act &= ~m;
     }
     if (!PAIRS) return live;
@@ -144,10 +130,13 @@ __device__ __forceinline__ bool wave_reduce(uint32_t pid, V val, bool live) {
 }
 
 // Sums of the HQ colour pass: lanes that share the first live lane's pixel
-// hand their (r<<32|g, b<<32|1) words to that lane (the all-lanes-equal
+// hand their red, green, blue and count to that lane (the all-lanes-equal
 // reduction of Sec. 3.3 applied to integer sums; exact because + commutes),
-// for up to two leaders per wavefront.  Must be called by the whole wave.
-__device__ __forceinline__ void wave_group_sums(uint32_t pid, u64 &rg, u64 &ba, bool &live) {
+// for up to two leaders per wavefront.  A wavefront adds at most 64 values of
+// at most 255, so two channels share one 32-bit word (16 bits each) without
+// carries; the leader unpacks them into the (r<<32|g, b<<32|count) words.
+// Must be called by the whole wave.
+__device__ __forceinline__ void wave_group_sums(uint32_t pid, uint32_t rgba, u64 &rg, u64 &ba, bool &live) {
     const uint32_t lane = __lane_id();
     uint64_t act = __ballot(live);
 #pragma unroll 1
@@ -157,11 +146,13 @@ __device__ __forceinline__ void wave_group_sums(uint32_t pid, u64 &rg, u64 &ba, 
         uint64_t m = __ballot(live && pid == p0);
         if (__popcll(m) < 4) break;
         bool in = (m >> lane) & 1ull;
-        u64 a = wave_sum(in ? rg : 0ull), b = wave_sum(in ? ba : 0ull);
+        const uint32_t w0 = (rgba & 0xFFu) | (rgba & 0xFF00u) << 8;    // r | g << 16
+        const uint32_t w1 = ((rgba >> 16) & 0xFFu) | 0x10000u;         // b | 1 << 16
+        const uint32_t a = wave_sum(in ? w0 : 0u), b = wave_sum(in ? w1 : 0u);
         if (in) {
             if (lane == leader) {
-                rg = a;
-                ba = b;
+                rg = (u64)(a & 0xFFFFu) << 32 | (a >> 16);
+                ba = (u64)(b & 0xFFFFu) << 32 | (b >> 16);
             } else {
                 live = false;
             }
@@ -261,8 +252,8 @@ __device__ __forceinline__ bool dense_collapse(const Lds<V> &L, uint32_t pid, V 
         uint32_t t0 = L.tag[L.home(p0)];
         if (t0 == p0) continue;  // slot exists: the early test filters
         bool in = (m >> lane) & 1ull;
-        V mv = wave_min(in ? val : (V)~(V)0);
-        if (in) live = val == mv;
+        const uint32_t md = wave_min(in ? depth_of(val) : ~0u);
+        if (in) live = depth_of(val) == md;  // the group's minimum is among these lanes
     }
     return live;
 }
@@ -590,7 +581,7 @@ __device__ __forceinline__ void hq_color_tiles(const u32x4 *__restrict__ pts, Ti
             bool live = pid != kEmptyPid && __uint_as_float(dbs[j]) <= __uint_as_float(dref[j]) * 1.01f;
             u64 r = p[j].w & 0xFFu, g = (p[j].w >> 8) & 0xFFu, bl = (p[j].w >> 16) & 0xFFu;
             u64 rg = (r << 32) | g, ba = (bl << 32) | 1u;
-            wave_group_sums(pid, rg, ba, live);
+            wave_group_sums(pid, p[j].w, rg, ba, live);
             if (!live) continue;
             if (!LDS) {
                 gadd_u64(S + 2 * (u64)pid, rg);

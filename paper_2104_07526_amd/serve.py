@@ -97,10 +97,15 @@ class Arena:
 class GpuBackend:
     """libpcr batch plans on torch streams.  Framebuffers are carved from one
     device arena (the admission budget); each request's image is its own
-    device tensor, written directly by the batch's resolve."""
+    device tensor, written directly by the batch's resolve.  The plans run
+    each view as its own single-view pass (tune group 1) unless ``tune`` says
+    otherwise: on large resident clouds the per-view passes are the faster
+    form (the batched pass is compute bound)."""
 
     def __init__(self, clouds, budget_bytes: int, capacity: int = 16, plans_per_cloud: int = 2,
                  tune=None, device="cuda", min_plan_views: int = 2):
+        if tune is None:
+            tune = {"group": 1}
         import torch
         self.torch = torch
         self.device = device
