@@ -44,10 +44,10 @@ HBM_PEAK_GBS = 8000.0
 # kernel sources they were taken on: `src` is the sha256 of the render sources.
 MEASURED_TRAFFIC = {
     # profiles/render_terrain100M_1080p.md
-    "k_basic": {"src": "0393fc077288ad283575500ff145be532fc35d3212070b7301c2ebb7571810f7",
-                "fetch_bytes": 1600013928, "write_bytes": 1282555392},
-    "k_dedup<u64>": {"src": "0393fc077288ad283575500ff145be532fc35d3212070b7301c2ebb7571810f7",
-                     "fetch_bytes": 1600190052, "write_bytes": 79971488},
+    "k_basic": {"src": "abe4ea323b0330b17e353b6e47f45c432ae595b6777ed1a40bbe36d3c8fa9844",
+                "fetch_bytes": 1600015244, "write_bytes": 1263360448},
+    "k_dedup<u64>": {"src": "abe4ea323b0330b17e353b6e47f45c432ae595b6777ed1a40bbe36d3c8fa9844",
+                     "fetch_bytes": 1600162312, "write_bytes": 113813963},
 }
 
 

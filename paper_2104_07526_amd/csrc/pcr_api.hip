@@ -54,10 +54,10 @@ static bool pow2_in(uint32_t v, uint32_t lo, uint32_t hi) {
 
 int resolve_shape(const pcr_tune *tune, int family, Shape &s) {
     // Defaults (measured on MI355X): a tile of 1024 points per 256-thread
-    // workgroup for the plain kernels, 2048 points and 1024 LDS slots for the
-    // deduplicating ones.
+    // workgroup for the basic kernel, 2048 points and 1024 LDS slots for the
+    // deduplicating and HQ ones.
     s.wg = 256;
-    s.ppt = family == PCR_DEDUP ? 8 : 4;
+    s.ppt = family == PCR_BASIC ? 4 : 8;
     s.grid = 0;
     s.group = 0;
     s.slots = 0;

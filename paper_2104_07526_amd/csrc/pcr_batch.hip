@@ -149,11 +149,12 @@ struct BLds {
         tag = (uint32_t *)(val + 2 * (1u << hbits));
         list = tag + (1u << hbits);
         mask = (1u << hbits) - 1u;
-        shift = 32u - hbits;
+        shift = 24u - hbits;  // hbits <= 15: the top bits of a 24-bit product
     }
     // Home slot of a (view slot, pixel) tag: the view bits are folded into
-    // the low 24 bits, then a full-rate 24-bit multiplicative hash (__umul24
-    // returns a signed int: shifted as unsigned and masked into the table).
+    // the low 24 bits, then Fibonacci hashing in a 24-bit word (full-rate
+    // 24-bit multiply; __umul24 returns a signed int: shifted as unsigned and
+    // masked into the table).
     __device__ __forceinline__ uint32_t home(uint32_t key) const {
         const uint32_t k = (key ^ (key >> 20)) & 0xFFFFFFu;
         return ((uint32_t)__umul24(k, 0x9E3779u) >> shift) & mask;

@@ -189,13 +189,14 @@ struct Lds {
         tag = (uint32_t *)(val + (1u << hbits));
         list = tag + (1u << hbits);
         mask = (1u << hbits) - 1u;
-        shift = 32u - hbits;
+        shift = 24u - hbits;  // hbits <= 15: the top bits of a 24-bit product
     }
 
-    // Home slot: multiplicative hash on a 24-bit multiply (full rate; the
-    // tag keeps the whole pixel index, the hash only spreads the slots).
-    // __umul24 returns a signed int: shift it as unsigned, and mask, so the
-    // index can never leave the table.
+    // Home slot: Fibonacci hashing in a 24-bit word (full-rate 24-bit
+    // multiply, top hbits of the low 24 bits of the product), which spreads
+    // runs of consecutive pixels like the 32-bit form; the tag keeps the whole
+    // pixel index, the hash only places it.  __umul24 returns a signed int:
+    // shifted as unsigned and masked, the index never leaves the table.
     __device__ __forceinline__ uint32_t home(uint32_t pid) const {
         return ((uint32_t)__umul24(pid, 0x9E3779u) >> shift) & mask;
     }
