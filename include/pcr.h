@@ -110,7 +110,10 @@ enum {
     PCR_ORDER_SHUFFLE = 2         /* sort by one random key per point */
 };
 
-/* Launch shape for the render kernels.  Zero fields take the defaults.
+/* Launch shape for the render kernels.  Zero fields take the defaults
+ * (measured on MI355X): basic 4 points per thread in 256-thread workgroups;
+ * deduplicating and HQ 8 points per thread in 64-thread (one-wavefront)
+ * workgroups with 256 LDS slots.
  *   ppt    points per thread (1, 2, 4, 8 or 16)
  *   wg     workgroup size (64, 128, 256, 512 or 1024)
  *   grid   workgroups per launch (0 = one tile of wg*ppt points per workgroup)
@@ -187,8 +190,9 @@ size_t pcr_chunks_scratch_bytes(uint32_t nchunks);
  *              256-byte aligned; overwritten (chunk start offsets).
  *   variant    PCR_BASIC, PCR_DEDUP or PCR_HQ, optionally with one PCR_F_HQ_*
  *              pass bit; the other flag bits give PCR_EUNSUPPORTED.
- *   tune       as pcr_render_ex (may be NULL); grid 0 = as many workgroups as
- *              are resident at once.
+ *   tune       as pcr_render_ex (may be NULL), except that the workgroup size
+ *              defaults to 256; grid 0 = as many workgroups as are resident at
+ *              once.
  * Errors: PCR_EINVAL (as pcr_render, plus NULL chunks with nchunks > 0,
  * nchunks > 2^24), PCR_ENOMEM (scratch too small). */
 int pcr_render_chunks(const pcr_chunk *chunks, uint32_t nchunks, const float mvp[16], uint32_t w,

@@ -54,9 +54,10 @@ static bool pow2_in(uint32_t v, uint32_t lo, uint32_t hi) {
 
 int resolve_shape(const pcr_tune *tune, int family, Shape &s) {
     // Defaults (measured on MI355X): a tile of 1024 points per 256-thread
-    // workgroup for the basic kernel, 2048 points and 1024 LDS slots for the
-    // deduplicating and HQ ones.
-    s.wg = 256;
+    // workgroup for the basic kernel; for the deduplicating and HQ ones,
+    // single-wavefront workgroups with 512-point tiles and 256 LDS slots
+    // (their barriers then never wait for another wavefront).
+    s.wg = family == PCR_BASIC ? 256 : 64;
     s.ppt = family == PCR_BASIC ? 4 : 8;
     s.grid = 0;
     s.group = 0;

@@ -500,7 +500,7 @@ extern "C" int pcr_batch_create(pcr_batch **plan, const pcr_point *pts, uint64_t
     if (n == 0 || !pts || ((uintptr_t)pts & 15)) return fail(PCR_EINVAL, "points must be a non-empty 16-byte aligned device buffer");
     pcr_tune t{};
     if (tune) t = *tune;
-    t.wg = kBatchWg;  // the batched kernels are built for 256-thread workgroups
+    if (t.group != 1) t.wg = kBatchWg;  // the batched kernels are built for 256-thread workgroups
     Shape sh;
     int rc = resolve_shape(&t, PCR_DEDUP, sh);
     if (rc != PCR_OK) return rc;

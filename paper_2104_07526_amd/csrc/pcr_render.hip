@@ -422,13 +422,14 @@ __global__ __launch_bounds__(1024) void k_basic(const u32x4 *__restrict__ pts, T
         uint64_t t;
         if (!src.tile(tl, b, t)) continue;
         const uint64_t first = t * wg * PPT;
-        const uint64_t base = first + threadIdx.x;
+        // Lanes of the tile that hold a point (uniform bound; 32-bit compares).
+        const uint32_t lim = tl.n - first < (uint64_t)wg * PPT ? (uint32_t)(tl.n - first) : wg * PPT;
         u32x4 p[PPT];
         src.template load<PPT>(pts, first, wg, tl.n, p);
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             uint32_t dbits;
-            uint32_t pid = project_wave(v, p[j], base + (uint64_t)j * wg < tl.n, dbits);
+            uint32_t pid = project_wave(v, p[j], (uint32_t)(j * wg + threadIdx.x) < lim, dbits);
             u64 key = make_key(dbits, p[j].w);
             bool w = pid != kEmptyPid;
             if (REDUCE) w = wave_reduce<u64, true>(pid, key, w);
@@ -468,13 +469,14 @@ __device__ __forceinline__ void dedup_tiles(const u32x4 *__restrict__ pts, Tiles
         uint64_t t;
         if (!src.tile(tl, b, t)) continue;
         const uint64_t first = t * wg * PPT;
-        const uint64_t base = first + threadIdx.x;
+        // Lanes of the tile that hold a point (uniform bound; 32-bit compares).
+        const uint32_t lim = tl.n - first < (uint64_t)wg * PPT ? (uint32_t)(tl.n - first) : wg * PPT;
         u32x4 p[PPT];
         src.template load<PPT>(pts, first, wg, tl.n, p);
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             uint32_t dbits;
-            uint32_t pid = project_wave(v, p[j], base + (uint64_t)j * wg < tl.n, dbits);
+            uint32_t pid = project_wave(v, p[j], (uint32_t)(j * wg + threadIdx.x) < lim, dbits);
             V val;
             if constexpr (sizeof(V) == 8)
                 val = make_key(dbits, p[j].w);
@@ -527,13 +529,14 @@ __global__ __launch_bounds__(1024) void k_hq_depth(const u32x4 *__restrict__ pts
         uint64_t t;
         if (!tl.tile(b, t)) continue;
         const uint64_t first = t * wg * PPT;
-        const uint64_t base = first + threadIdx.x;
+        // Lanes of the tile that hold a point (uniform bound; 32-bit compares).
+        const uint32_t lim = tl.n - first < (uint64_t)wg * PPT ? (uint32_t)(tl.n - first) : wg * PPT;
         u32x4 p[PPT];
         load_tile<PPT>(pts, first, wg, tl.n, p);
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             uint32_t dbits;
-            uint32_t pid = project_wave(v, p[j], base + (uint64_t)j * wg < tl.n, dbits);
+            uint32_t pid = project_wave(v, p[j], (uint32_t)(j * wg + threadIdx.x) < lim, dbits);
             bool w = pid != kEmptyPid;
             if (EARLYZ && w) w = dbits < peek_u32(D + pid);
             if (w) gmin_u32(D + pid, dbits);
@@ -566,14 +569,15 @@ __device__ __forceinline__ void hq_color_tiles(const u32x4 *__restrict__ pts, Ti
         uint64_t t;
         if (!src.tile(tl, b, t)) continue;
         const uint64_t first = t * wg * PPT;
-        const uint64_t base = first + threadIdx.x;
+        // Lanes of the tile that hold a point (uniform bound; 32-bit compares).
+        const uint32_t lim = tl.n - first < (uint64_t)wg * PPT ? (uint32_t)(tl.n - first) : wg * PPT;
         u32x4 p[PPT];
         src.template load<PPT>(pts, first, wg, tl.n, p);
         // Project every point first, then read all their closest depths back
         // to back (one round trip for the tile instead of one per point).
         uint32_t pids[PPT], dbs[PPT], dref[PPT];
 #pragma unroll
-        for (int j = 0; j < PPT; ++j) pids[j] = project_wave(v, p[j], base + (uint64_t)j * wg < tl.n, dbs[j]);
+        for (int j = 0; j < PPT; ++j) pids[j] = project_wave(v, p[j], (uint32_t)(j * wg + threadIdx.x) < lim, dbs[j]);
 #pragma unroll
         for (int j = 0; j < PPT; ++j) dref[j] = D[pids[j] != kEmptyPid ? pids[j] : 0u];
 #pragma unroll
@@ -1104,6 +1108,9 @@ extern "C" int pcr_render_chunks(const pcr_chunk *chunks, uint32_t nchunks, cons
     Shape sh;
     rc = resolve_shape(tune, fam, sh);
     if (rc != PCR_OK) return rc;
+    // Persistent workgroups walk the chunk table once per tile: larger tiles
+    // (256 threads) amortise that walk, unless the caller chose a size.
+    if (!tune || tune->wg == 0) sh.wg = 256;
     if (nchunks == 0) return PCR_OK;
     if (!chunks || ((uintptr_t)chunks & 7)) return fail(PCR_EINVAL, "chunks must be an 8-byte aligned device pointer");
     if (!scratch || ((uintptr_t)scratch & 15)) return fail(PCR_EINVAL, "scratch must be a 16-byte aligned device pointer");

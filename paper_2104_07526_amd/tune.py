@@ -20,8 +20,8 @@ _lock = threading.Lock()
 
 # group 1: each view its own single-view pass inside the plan's graph
 BATCH_CANDIDATES = [{"ppt": p, "group": g} for p in (4, 8) for g in (1, 4, 8, 16, 32)]
-RENDER_CANDIDATES = [{"ppt": p, "wg": w, "slots": s} for p in (4, 8, 16) for w in (256, 512)
-                     for s in (0, 1024, 2048)]
+RENDER_CANDIDATES = [{"ppt": p, "wg": w, "slots": s} for p in (4, 8, 16) for w in (64, 128, 256, 512)
+                     for s in (0, 512, 1024, 2048)]
 
 
 def _device():
