@@ -268,7 +268,8 @@ typedef struct pcr_view {
  * image is bit-identical to pcr_fb_clear + pcr_render + pcr_resolve of that
  * view alone.  The plan allocates its device view table and graph at
  * creation; pcr_batch_launch allocates nothing.  A plan is not thread-safe;
- * launches of one plan on different streams must not overlap. */
+ * a launch on another stream than the previous one waits for it on the
+ * device (launches of one plan never overlap). */
 typedef struct pcr_batch pcr_batch;
 
 int pcr_batch_create(pcr_batch **plan, const pcr_point *pts, uint64_t n, uint32_t capacity,
@@ -279,6 +280,20 @@ int pcr_batch_create(pcr_batch **plan, const pcr_point *pts, uint64_t n, uint32_
 int pcr_batch_launch(pcr_batch *plan, const pcr_view *views, uint32_t nviews, void *stream);
 
 int pcr_batch_destroy(pcr_batch *plan);
+
+/* One-call form of a batch (the views of one launch, as pcr_batch_launch):
+ * the library keeps up to 8 plans, keyed by device, point buffer, n, launch
+ * shape and capacity (nviews rounded up to a power of two, at least 4), and
+ * creates one on the first call with a new key (that call allocates; calls
+ * that reuse a plan allocate nothing).  A cached plan refers to `pts`: call
+ * pcr_release_batch_plans before freeing a point buffer that was batched.
+ * Thread-safe; launches of one cached plan on different streams are ordered.
+ * nviews == 0 is a no-op; errors as pcr_batch_create / pcr_batch_launch. */
+int pcr_render_batch(const pcr_point *pts, uint64_t n, const pcr_view *views, uint32_t nviews,
+                     const pcr_tune *tune, void *stream);
+
+/* Destroys every cached plan of pcr_render_batch (waits for their launches). */
+int pcr_release_batch_plans(void);
 
 /* Self-check of the projection's reciprocal (see the Projection paragraph):
  * adds to *mismatches (device, uint64, 8-byte aligned) the number of floats

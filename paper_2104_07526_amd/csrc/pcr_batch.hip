@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "pcr_internal.h"
@@ -371,6 +372,7 @@ struct pcr_batch {
     unsigned char *staging[kRing] = {};
     hipEvent_t done[kRing] = {};
     int next = 0;
+    int last = -1;  // staging slot of the previous launch (its event marks its end)
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -630,9 +632,77 @@ extern "C" int pcr_batch_launch(pcr_batch *b, const pcr_view *views, uint32_t nv
     if (B.sh.group == 1)
         if (int rc = select_view_nodes(b, dv)) return rc;
     hipStream_t s = (hipStream_t)stream;
+    // The plan's device table is rewritten below: on another stream, wait for
+    // the previous launch of this plan first (a no-op on the same stream).
+    if (B.last >= 0) PCR_HIP(hipStreamWaitEvent(s, B.done[B.last], 0));
     PCR_HIP(hipMemcpyAsync(B.dtable, st, B.lay.bytes, hipMemcpyHostToDevice, s));
     PCR_HIP(hipGraphLaunch(B.exec, s));
     PCR_HIP(hipEventRecord(B.done[slot], s));
+    B.last = slot;
+    return PCR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// One-call batches over a small cache of plans
+// ---------------------------------------------------------------------------
+namespace {
+
+struct CachedPlan {
+    int device;
+    const pcr_point *pts;
+    uint64_t n;
+    uint32_t capacity;
+    pcr_tune tune;
+    pcr_batch *plan;
+    uint64_t used;
+};
+
+std::mutex g_cache_mu;
+std::vector<CachedPlan> g_cache;
+uint64_t g_cache_tick = 0;
+constexpr size_t kCachedPlans = 8;
+
+bool same_tune(const pcr_tune &a, const pcr_tune &b) {
+    return a.ppt == b.ppt && a.wg == b.wg && a.grid == b.grid && a.group == b.group && a.slots == b.slots;
+}
+
+}  // namespace
+
+extern "C" int pcr_render_batch(const pcr_point *pts, uint64_t n, const pcr_view *views, uint32_t nviews,
+                                const pcr_tune *tune, void *stream) {
+    if (nviews == 0) return PCR_OK;
+    if (!views) return fail(PCR_EINVAL, "views is NULL");
+    if (nviews > 4096) return fail(PCR_EINVAL, "%u views exceed 4096", nviews);
+    int dev = 0;
+    PCR_HIP(hipGetDevice(&dev));
+    pcr_tune t{};
+    if (tune) t = *tune;
+    uint32_t cap = 4;
+    while (cap < nviews) cap *= 2;
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    CachedPlan *hit = nullptr;
+    for (auto &c : g_cache)
+        if (c.device == dev && c.pts == pts && c.n == n && c.capacity == cap && same_tune(c.tune, t)) hit = &c;
+    if (!hit) {
+        if (g_cache.size() >= kCachedPlans) {  // drop the least recently used plan
+            auto lru = std::min_element(g_cache.begin(), g_cache.end(),
+                                        [](const CachedPlan &a, const CachedPlan &b) { return a.used < b.used; });
+            pcr_batch_destroy(lru->plan);
+            g_cache.erase(lru);
+        }
+        pcr_batch *plan = nullptr;
+        if (int rc = pcr_batch_create(&plan, pts, n, cap, tune ? &t : nullptr, stream)) return rc;
+        g_cache.push_back(CachedPlan{dev, pts, n, cap, t, plan, 0});
+        hit = &g_cache.back();
+    }
+    hit->used = ++g_cache_tick;
+    return pcr_batch_launch(hit->plan, views, nviews, stream);
+}
+
+extern "C" int pcr_release_batch_plans(void) {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    for (auto &c : g_cache) pcr_batch_destroy(c.plan);
+    g_cache.clear();
     return PCR_OK;
 }
 

@@ -71,6 +71,8 @@ def _declare(lib):
         "pcr_batch_create": (I32, [P, P, U64, U32, P, P]),
         "pcr_batch_launch": (I32, [P, P, U32, P]),
         "pcr_batch_destroy": (I32, [P]),
+        "pcr_render_batch": (I32, [P, U64, P, U32, P, P]),
+        "pcr_release_batch_plans": (I32, []),
         "pcr_check_reciprocal": (I32, [U32, U32, P, P]),
         "pcr_last_error": (ctypes.c_char_p, []),
         "pcr_version": (ctypes.c_char_p, []),
@@ -255,6 +257,17 @@ def make_view(mvp, w, h, variant, fb, rgba_out) -> View:
     v.fb = _ptr(fb)
     v.rgba_out = _ptr(rgba_out)
     return v
+
+
+def render_batch(points, views, tune=None, stream=None):
+    """One-call batch of pcr.View records over the library's plan cache
+    (pcr_render_batch in include/pcr.h)."""
+    arr = (View * max(1, len(views)))(*views)
+    _check(lib().pcr_render_batch(_ptr(points), _npoints(points), arr, len(views), _tune(tune), _stream(stream)))
+
+
+def release_batch_plans():
+    _check(lib().pcr_release_batch_plans())
 
 
 class BatchPlan:

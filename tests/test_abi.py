@@ -111,6 +111,13 @@ def test_chunk_argument_checks():
         pcr.EUNSUPPORTED
 
 
+def test_render_batch_argument_checks():
+    L = pcr.lib()
+    assert L.pcr_render_batch(16, 100, None, 0, None, None) == pcr.OK          # nothing to do
+    assert L.pcr_render_batch(16, 100, None, 3, None, None) == pcr.EINVAL
+    assert L.pcr_release_batch_plans() == pcr.OK
+
+
 def test_reorder_argument_checks():
     L = pcr.lib()
     assert L.pcr_reorder_scratch_bytes(1000, 5, 128) == 0

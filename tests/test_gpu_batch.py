@@ -166,3 +166,32 @@ def test_back_to_back_launches_of_varying_size(orc, scene, tune):
             _, eimg = oracle_frame(orc, pts, m, W, H, var)
             assert np.array_equal(img.cpu().numpy().view(np.uint32), eimg), (k, var)
     plan.close()
+
+
+def test_one_call_batches_over_cached_plans(orc, scene):
+    """pcr_render_batch: view sets of 3 and 7 (two cached plans), and the same
+    plan launched on two streams back to back without waiting; every image
+    equals the oracle."""
+    import torch
+    pts, d = scene
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    runs = []
+    for k, (cnt, stream) in enumerate(((3, None), (7, None), (3, s1), (3, s2), (7, s1))):
+        views = make_views(cnt, seed=500 + k)
+        bufs, pv = [], []
+        for m, W, H, var in views:
+            fb = pcr.alloc_fb(W, H, var)
+            img = torch.zeros(W * H, dtype=torch.int32, device="cuda")
+            bufs.append((fb, img))
+            pv.append(pcr.make_view(m, W, H, var, fb, img))
+        if stream is not None:
+            stream.wait_stream(torch.cuda.current_stream())   # the zeroed images
+        pcr.render_batch(d, pv, stream=stream)
+        runs.append((views, bufs))
+    torch.cuda.synchronize()
+    for k, (views, bufs) in enumerate(runs):
+        for (m, W, H, var), (fb, img) in zip(views, bufs):
+            _, eimg = oracle_frame(orc, pts, m, W, H, var)
+            assert np.array_equal(img.cpu().numpy().view(np.uint32), eimg), (k, var)
+    pcr.release_batch_plans()
