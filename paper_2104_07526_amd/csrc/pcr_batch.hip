@@ -206,9 +206,10 @@ __global__ __launch_bounds__(kBatchWg) void k_batch_pass(const u32x4 *__restrict
     BLds S(smem, hbits);
     Table t = table(base, L);
     const uint32_t HS = 1u << hbits;
-    const uint32_t T = kBatchWg * PPT;
+    const uint32_t wg = blockDim.x;  // 64, 128 or 256
+    const uint32_t T = wg * PPT;
     const uint64_t ntiles = (n + T - 1) / T;
-    for (uint32_t s = threadIdx.x; s < HS; s += kBatchWg) {
+    for (uint32_t s = threadIdx.x; s < HS; s += wg) {
         S.tag[s] = kEmptyPid;
         S.val[2 * s] = PASS ? 0ull : kEmptyKey;
         S.val[2 * s + 1] = 0ull;
@@ -222,7 +223,7 @@ __global__ __launch_bounds__(kBatchWg) void k_batch_pass(const u32x4 *__restrict
         const uint32_t cnt = *S.count;
         bar_lds();
         if (threadIdx.x == 0) *S.count = 0;
-        for (uint32_t k = threadIdx.x; k < cnt; k += kBatchWg) {
+        for (uint32_t k = threadIdx.x; k < cnt; k += wg) {
             uint32_t h = S.list[k];
             uint32_t tag = S.tag[h];
             uint32_t vs = tag >> kPidBits, pid = tag & kPidMask;
@@ -272,7 +273,7 @@ __global__ __launch_bounds__(kBatchWg) void k_batch_pass(const u32x4 *__restrict
         u32x4 p[PPT];
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
-            uint32_t k = (uint32_t)(j * kBatchWg + threadIdx.x);
+            uint32_t k = (uint32_t)(j * wg + threadIdx.x);
             p[j] = load_point(pts + first + (k < rem ? k : (uint32_t)(rem - 1)));
         }
         if (g != cur_g) {
@@ -297,7 +298,7 @@ __global__ __launch_bounds__(kBatchWg) void k_batch_pass(const u32x4 *__restrict
             uint32_t pids[PPT], dbs[PPT];
 #pragma unroll
             for (int j = 0; j < PPT; ++j)
-                pids[j] = project_wave(v, p[j], (uint64_t)(j * kBatchWg + threadIdx.x) < rem, dbs[j]);
+                pids[j] = project_wave(v, p[j], (uint64_t)(j * wg + threadIdx.x) < rem, dbs[j]);
             if (PASS == 0) {
 #pragma unroll
                 for (int j = 0; j < PPT; ++j) {
@@ -389,9 +390,9 @@ namespace {
 
 // Workgroups of a persistent pass: as many as are resident at once on the
 // device, so that no workgroup waits for another to finish its whole share.
-int resident_grid(const void *fn, size_t sm, uint32_t &grid) {
+int resident_grid(const void *fn, uint32_t wg, size_t sm, uint32_t &grid) {
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, (int)kBatchWg, sm);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, (int)wg, sm);
     if (e != hipSuccess || per_cu <= 0) return fail(PCR_EHIP, "occupancy query failed: %s", hipGetErrorString(e));
     grid = (uint32_t)per_cu * (uint32_t)device_cus();
     return PCR_OK;
@@ -405,15 +406,15 @@ int launch_pass(pcr_batch *b, int pass, hipStream_t s) {
         if (pass < 0) {                                                                                \
             int rc = allow_lds((const void *)&k_batch_pass<P, 0>, sm);                                 \
             if (rc == PCR_OK) rc = allow_lds((const void *)&k_batch_pass<P, 1>, sm);                   \
-            if (rc == PCR_OK) rc = resident_grid((const void *)&k_batch_pass<P, 0>, sm, b->grid_pass[0]); \
-            if (rc == PCR_OK) rc = resident_grid((const void *)&k_batch_pass<P, 1>, sm, b->grid_pass[1]); \
+            if (rc == PCR_OK) rc = resident_grid((const void *)&k_batch_pass<P, 0>, b->sh.wg, sm, b->grid_pass[0]); \
+            if (rc == PCR_OK) rc = resident_grid((const void *)&k_batch_pass<P, 1>, b->sh.wg, sm, b->grid_pass[1]); \
             return rc;                                                                                 \
         }                                                                                              \
         if (pass)                                                                                      \
-            hipLaunchKernelGGL((k_batch_pass<P, 1>), dim3(b->grid_pass[1]), dim3(kBatchWg), sm, s, b->pts, b->n, \
+            hipLaunchKernelGGL((k_batch_pass<P, 1>), dim3(b->grid_pass[1]), dim3(b->sh.wg), sm, s, b->pts, b->n, \
                                b->dtable, b->lay, b->hbits);                                           \
         else                                                                                           \
-            hipLaunchKernelGGL((k_batch_pass<P, 0>), dim3(b->grid_pass[0]), dim3(kBatchWg), sm, s, b->pts, b->n, \
+            hipLaunchKernelGGL((k_batch_pass<P, 0>), dim3(b->grid_pass[0]), dim3(b->sh.wg), sm, s, b->pts, b->n, \
                                b->dtable, b->lay, b->hbits);                                           \
         break;
     switch (b->sh.ppt) {
@@ -502,7 +503,10 @@ extern "C" int pcr_batch_create(pcr_batch **plan, const pcr_point *pts, uint64_t
     if (n == 0 || !pts || ((uintptr_t)pts & 15)) return fail(PCR_EINVAL, "points must be a non-empty 16-byte aligned device buffer");
     pcr_tune t{};
     if (tune) t = *tune;
-    if (t.group != 1) t.wg = kBatchWg;  // the batched kernels are built for 256-thread workgroups
+    if (t.group != 1) {  // the batched pass runs 64-, 128- or 256-thread workgroups
+        if (t.wg == 0) t.wg = kBatchWg;
+        if (t.wg > kBatchWg) return fail(PCR_EINVAL, "batched passes take at most %u threads per workgroup", kBatchWg);
+    }
     Shape sh;
     int rc = resolve_shape(&t, PCR_DEDUP, sh);
     if (rc != PCR_OK) return rc;
@@ -511,7 +515,7 @@ extern "C" int pcr_batch_create(pcr_batch **plan, const pcr_point *pts, uint64_t
     b->n = n;
     b->capacity = capacity;
     b->sh = sh;
-    uint32_t want = sh.slots ? sh.slots : kBatchWg * sh.ppt / 2;
+    uint32_t want = sh.slots ? sh.slots : sh.wg * sh.ppt / 2;
     b->hbits = 8;
     while ((1u << b->hbits) < want && b->hbits < 14) ++b->hbits;
     if (batch_lds(b->hbits) > max_lds()) {

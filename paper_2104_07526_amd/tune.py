@@ -19,7 +19,8 @@ CACHE = os.environ.get("PCR_TUNE_CACHE", os.path.join(os.path.expanduser("~"), "
 _lock = threading.Lock()
 
 # group 1: each view its own single-view pass inside the plan's graph
-BATCH_CANDIDATES = [{"ppt": p, "group": g} for p in (4, 8) for g in (1, 4, 8, 16, 32)]
+BATCH_CANDIDATES = ([{"ppt": p, "group": g} for p in (4, 8) for g in (1, 4, 8, 16, 32)] +
+                    [{"ppt": 8, "group": g, "wg": 64} for g in (4, 8, 16, 32)])
 RENDER_CANDIDATES = [{"ppt": p, "wg": w, "slots": s} for p in (4, 8, 16) for w in (64, 128, 256, 512)
                      for s in (0, 512, 1024, 2048)]
 

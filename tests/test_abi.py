@@ -139,5 +139,8 @@ def test_batch_argument_checks():
     assert L.pcr_batch_create(ctypes.byref(h), 16, 100, 0, None, None) == pcr.EINVAL
     assert L.pcr_batch_create(ctypes.byref(h), 8, 100, 4, None, None) == pcr.EINVAL
     assert L.pcr_batch_create(ctypes.byref(h), 16, 0, 4, None, None) == pcr.EINVAL
+    tune = pcr.Tune(8, 512, 0, 4, 0)          # batched pass above 256 threads per workgroup
+    assert L.pcr_batch_create(ctypes.byref(h), 16, 100, 4, ctypes.byref(tune), None) == pcr.EINVAL
+    assert "workgroup" in L.pcr_last_error().decode()
     assert L.pcr_batch_launch(None, None, 0, None) == pcr.EINVAL
     assert L.pcr_batch_destroy(None) == pcr.OK

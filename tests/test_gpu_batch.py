@@ -41,7 +41,8 @@ def scene():
 
 
 @pytest.mark.parametrize("tune", [None, {"ppt": 4}, {"ppt": 8, "group": 2}, {"ppt": 16, "slots": 256},
-                                  {"ppt": 8, "group": 1}, {"ppt": 2, "group": 1, "slots": 256}])
+                                  {"ppt": 8, "group": 1}, {"ppt": 2, "group": 1, "slots": 256},
+                                  {"ppt": 8, "group": 4, "wg": 64}, {"ppt": 4, "group": 16, "wg": 128}])
 def test_views_match_oracle(orc, scene, tune):
     pts, d = scene
     views = make_views(9, seed=11)
@@ -130,7 +131,8 @@ def test_many_views_fill_the_shared_table(orc):
     for i, (eye, tgt, up) in enumerate(synth.random_poses(16, seed=77)):
         W, H = [(320, 180), (256, 256)][i % 2]
         views.append((synth.mvp(eye, tgt, up, W, H), W, H, [pcr.BASIC, pcr.HQ][i % 2]))
-    for tune in ({"ppt": 4, "group": 16, "slots": 256}, {"ppt": 8, "group": 16, "slots": 256}):
+    for tune in ({"ppt": 4, "group": 16, "slots": 256}, {"ppt": 8, "group": 16, "slots": 256},
+                 {"ppt": 8, "group": 16, "wg": 64}):
         plan = pcr.BatchPlan(d, capacity=16, tune=tune)
         for _ in range(2):
             bufs = run_batch(plan, views)
