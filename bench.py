@@ -44,10 +44,10 @@ HBM_PEAK_GBS = 8000.0
 # kernel sources they were taken on: `src` is the sha256 of the render sources.
 MEASURED_TRAFFIC = {
     # profiles/render_terrain100M_1080p.md
-    "k_basic": {"src": "c24d3bcf8116a4e13372e20bcae7be82f003f6fc49a025c956fcb9b8170be8bc",
-                "fetch_bytes": 1600009176, "write_bytes": 1263360448},
-    "k_dedup<u64>": {"src": "c24d3bcf8116a4e13372e20bcae7be82f003f6fc49a025c956fcb9b8170be8bc",
-                     "fetch_bytes": 1600157609, "write_bytes": 111195744},
+    "k_basic": {"src": "4127dcfe6857eee65b9f2a9f1481aa755afb6b062ce604cce2c1adc8e3c570eb",
+                "fetch_bytes": 1600015497, "write_bytes": 1263360448},
+    "k_dedup<u64>": {"src": "4127dcfe6857eee65b9f2a9f1481aa755afb6b062ce604cce2c1adc8e3c570eb",
+                     "fetch_bytes": 1600172592, "write_bytes": 111195744},
 }
 
 

@@ -111,12 +111,15 @@ enum {
 };
 
 /* Launch shape for the render kernels.  Zero fields take the defaults
- * (measured on MI355X): basic 4 points per thread in 256-thread workgroups;
- * deduplicating and HQ 8 points per thread in 64-thread (one-wavefront)
- * workgroups with 256 LDS slots.
+ * (measured on MI355X): basic 4 points per thread in 256-thread workgroups,
+ * one tile per workgroup; deduplicating and HQ 8 points per thread in
+ * 64-thread (one-wavefront) workgroups with 256 LDS slots, 512 workgroups per
+ * compute unit stepping over the tiles.
  *   ppt    points per thread (1, 2, 4, 8 or 16)
  *   wg     workgroup size (64, 128, 256, 512 or 1024)
- *   grid   workgroups per launch (0 = one tile of wg*ppt points per workgroup)
+ *   grid   workgroups per launch; each takes tiles g, g + grid, ... (0 = the
+ *          default above; a basic render's default is one tile of wg*ppt
+ *          points per workgroup, XCD-contiguous)
  *   group  views per point pass in a batch (0 = all that fit the cache budget;
  *          1 = every view its own pass with the single-view kernels)
  *   slots  LDS hash-table slots per workgroup of the deduplicating kernels,
@@ -190,9 +193,9 @@ size_t pcr_chunks_scratch_bytes(uint32_t nchunks);
  *              256-byte aligned; overwritten (chunk start offsets).
  *   variant    PCR_BASIC, PCR_DEDUP or PCR_HQ, optionally with one PCR_F_HQ_*
  *              pass bit; the other flag bits give PCR_EUNSUPPORTED.
- *   tune       as pcr_render_ex (may be NULL), except that the workgroup size
- *              defaults to 256; grid 0 = as many workgroups as are resident at
- *              once.
+ *   tune       as pcr_render_ex (may be NULL); grid 0 = as many workgroups as
+ *              are resident at once.  Tiles of wg*ppt points never span two
+ *              chunks (the last tile of a chunk is partial).
  * Errors: PCR_EINVAL (as pcr_render, plus NULL chunks with nchunks > 0,
  * nchunks > 2^24), PCR_ENOMEM (scratch too small). */
 int pcr_render_chunks(const pcr_chunk *chunks, uint32_t nchunks, const float mvp[16], uint32_t w,

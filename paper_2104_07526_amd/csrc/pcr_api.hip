@@ -57,15 +57,18 @@ int resolve_shape(const pcr_tune *tune, int family, Shape &s) {
     // workgroup for the basic kernel; for the deduplicating and HQ ones,
     // single-wavefront workgroups with 512-point tiles and 256 LDS slots
     // (their barriers then never wait for another wavefront).
+    // They step over the tiles in their natural order with 512 workgroups per
+    // CU, which beat one workgroup per tile on every measured order (the
+    // basic kernel keeps one tile per workgroup).
     s.wg = family == PCR_BASIC ? 256 : 64;
     s.ppt = family == PCR_BASIC ? 4 : 8;
-    s.grid = 0;
+    s.grid = family == PCR_BASIC ? 0 : 512u * (uint32_t)device_cus();
     s.group = 0;
     s.slots = 0;
     if (tune) {
         if (tune->wg) s.wg = tune->wg;
         if (tune->ppt) s.ppt = tune->ppt;
-        s.grid = tune->grid;
+        if (tune->grid) s.grid = tune->grid;
         s.group = tune->group;
         s.slots = tune->slots;
     }

@@ -116,8 +116,10 @@ __device__ __forceinline__ uint32_t project_wave(const View &v, const u32x4 &p, 
     return live ? pid : kEmptyPid;
 }
 
+// Non-temporal 16-byte point load, addressed as global memory (point
+// buffers are device memory; a generic load would also wait on LDS traffic).
 __device__ __forceinline__ u32x4 load_point(const u32x4 *p) {
-    return __builtin_nontemporal_load(p);
+    return __builtin_nontemporal_load((const __attribute__((address_space(1))) u32x4 *)p);
 }
 
 __device__ __forceinline__ u64 make_key(uint32_t dbits, uint32_t rgba) {

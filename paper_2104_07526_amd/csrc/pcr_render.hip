@@ -306,108 +306,75 @@ __device__ __forceinline__ void load_tile(const u32x4 *__restrict__ pts, uint64_
     }
 }
 
-// Point sources of the render kernels.  FlatSrc: one contiguous buffer (the
-// kernel's `pts` argument), one tile per workgroup.  ChunkSrc: the
-// concatenation of many separate buffers (level-of-detail chunks, Sec. 5.4);
-// tiles run over the virtual concatenation, so small chunks share tiles and no
-// lane idles at a chunk's end.  start[c] is the first virtual index of chunk c
-// and start[nchunks] the total, written on the device by k_chunk_starts, so
-// the tile count is only known inside the kernel (setup()).
+// Point sources of the render kernels.  load() fills the tile's points and
+// returns how many lanes of the tile hold one.  FlatSrc: one contiguous buffer
+// (the kernel's `pts` argument), one tile per workgroup.  ChunkSrc: many
+// separate buffers (level-of-detail chunks, Sec. 5.4), tiled chunk by chunk so
+// that a tile never spans two chunks: every lane loads from one uniform base
+// exactly as in the flat case, and only the last tile of a chunk is partial.
+// start[c] is the first tile of chunk c and start[nchunks] the tile count,
+// written on the device by k_chunk_starts, so the tile count is only known
+// inside the kernel (setup()).
 struct FlatSrc {
     static constexpr bool chunked = false;
     __device__ __forceinline__ void setup(Tiles &, uint32_t) {}
     __device__ __forceinline__ bool tile(const Tiles &tl, uint64_t b, uint64_t &t) { return tl.tile(b, t); }
     template <int PPT>
-    __device__ __forceinline__ void load(const u32x4 *__restrict__ pts, uint64_t first, uint32_t wg, uint64_t n,
-                                         u32x4 (&p)[PPT]) {
+    __device__ __forceinline__ uint32_t load(const u32x4 *__restrict__ pts, uint64_t t, uint32_t wg, uint64_t n,
+                                             u32x4 (&p)[PPT]) {
+        const uint64_t first = t * wg * PPT;
         load_tile<PPT>(pts, first, wg, n, p);
+        return n - first < (uint64_t)wg * PPT ? (uint32_t)(n - first) : wg * PPT;
     }
 };
 
 struct ChunkSrc {
     static constexpr bool chunked = true;
-    static constexpr int K = 4;  // chunks a tile may span on the fast path
     const pcr_chunk *chunks;
     const uint64_t *start;
     uint32_t nchunks;
     // Per workgroup (set up in the kernel): the contiguous tile range
-    // [t_next, t_end) and the chunk holding the next tile's first point.
+    // [t_next, t_end) and the chunk holding tile t_next.
     uint64_t t_next, t_end;
     uint32_t cur;
 
-    // Last c with start[c] <= g (start[0] = 0 <= g < start[nchunks]).
-    __device__ __forceinline__ uint32_t find(uint64_t g) const {
+    // Last c with start[c] <= t (start[0] = 0 <= t < start[nchunks]).
+    __device__ __forceinline__ uint32_t find(uint64_t t) const {
         uint32_t lo = 0, hi = nchunks;
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) / 2;
-            if (start[mid] <= g) lo = mid;
+            if (start[mid] <= t) lo = mid;
             else hi = mid;
         }
         return lo;
     }
 
-    // Static XCD-aware schedule: workgroups are dispatched round-robin over
-    // the 8 XCDs; the workgroups of XCD x split the x-th eighth of the tiles
-    // into contiguous ranges, so a workgroup's tiles follow each other and its
-    // chunk cursor only moves forward (no search per tile).
-    __device__ __forceinline__ void setup(Tiles &tl, uint32_t T) {
-        const uint64_t n = start[nchunks];
-        tl.n = n;
-        tl.ntiles = (n + T - 1) / T;
-        const uint32_t nx = gridDim.x < 8u ? gridDim.x : 8u;
-        const uint32_t xcd = blockIdx.x % nx, lane_wg = blockIdx.x / nx;
-        const uint32_t wgs_x = (gridDim.x - xcd + nx - 1u) / nx;
-        const uint64_t per_x = (tl.ntiles + nx - 1) / nx;
-        const uint64_t x_lo = xcd * per_x < tl.ntiles ? xcd * per_x : tl.ntiles;
-        const uint64_t x_hi = x_lo + per_x < tl.ntiles ? x_lo + per_x : tl.ntiles;
-        const uint64_t per_wg = (x_hi - x_lo + wgs_x - 1) / wgs_x;
-        const uint64_t lo = x_lo + lane_wg * per_wg;
-        t_next = lo < x_hi ? lo : x_hi;
-        t_end = t_next + per_wg < x_hi ? t_next + per_wg : x_hi;
+    // Static schedule: workgroup b takes the b-th contiguous range of tiles,
+    // so its chunk cursor only moves forward (no search per tile), and the
+    // workgroups resident at one time cover one window of the tile order (the
+    // order that the flat kernels' grid-stride schedule also follows).
+    __device__ __forceinline__ void setup(Tiles &tl, uint32_t) {
+        tl.ntiles = start[nchunks];
+        const uint64_t per_wg = (tl.ntiles + gridDim.x - 1) / gridDim.x;
+        const uint64_t lo = (uint64_t)blockIdx.x * per_wg;
+        t_next = lo < tl.ntiles ? lo : tl.ntiles;
+        t_end = t_next + per_wg < tl.ntiles ? t_next + per_wg : tl.ntiles;
         tl.nblocks = blockIdx.x + (t_end - t_next) * gridDim.x;  // this workgroup's loop count
-        cur = t_next < t_end ? find(t_next * T) : 0u;
+        cur = t_next < t_end ? find(t_next) : 0u;
     }
     __device__ __forceinline__ bool tile(const Tiles &, uint64_t, uint64_t &t) {
         t = t_next++;
         return true;
     }
     template <int PPT>
-    __device__ __forceinline__ void load(const u32x4 *__restrict__, uint64_t first, uint32_t wg, uint64_t n,
-                                         u32x4 (&p)[PPT]) {
-        while (start[cur + 1] <= first) ++cur;  // uniform, usually 0 or 1 step
-        // Window of the next K chunks: their starts and buffers, uniform.
-        uint64_t s[K + 1];
-        const u32x4 *b[K];
-#pragma unroll
-        for (int k = 0; k <= K; ++k) s[k] = start[cur + k < nchunks ? cur + k : nchunks];
-#pragma unroll
-        for (int k = 0; k < K; ++k) b[k] = (const u32x4 *)chunks[cur + k < nchunks ? cur + k : nchunks - 1].pts;
-#pragma unroll
-        for (int j = 0; j < PPT; ++j) {
-            uint64_t g = first + (uint64_t)(j * wg + threadIdx.x);
-            if (g >= n) g = n - 1;  // lanes past the end: discarded by the caller
-            // Chunk offset in the window: boundaries passed (empty chunks
-            // have equal starts and are passed together with their successor).
-            uint32_t k = 0;
-#pragma unroll
-            for (int q = 1; q <= K; ++q) k += g >= s[q] ? 1u : 0u;
-            const u32x4 *base = b[0];
-            uint64_t sb = s[0];
-#pragma unroll
-            for (int q = 1; q < K; ++q) {
-                base = k == (uint32_t)q ? b[q] : base;
-                sb = k == (uint32_t)q ? s[q] : sb;
-            }
-            if (k == (uint32_t)K) {  // more than K chunks in this tile: walk
-                uint32_t c = cur + K;
-                while (start[c + 1] <= g) ++c;
-                base = (const u32x4 *)chunks[c].pts;
-                sb = start[c];
-            }
-            // The buffer addresses come from memory, so name the global
-            // address space (a generic load would also wait on LDS traffic).
-            p[j] = __builtin_nontemporal_load((const __attribute__((address_space(1))) u32x4 *)(base + (g - sb)));
-        }
+    __device__ __forceinline__ uint32_t load(const u32x4 *__restrict__, uint64_t t, uint32_t wg, uint64_t,
+                                             u32x4 (&p)[PPT]) {
+        while (start[cur + 1] <= t) ++cur;  // uniform; skips empty and skipped chunks
+        const u32x4 *base = (const u32x4 *)chunks[cur].pts;
+        const uint64_t cn = chunks[cur].n;
+        const uint64_t first = (t - start[cur]) * wg * PPT;  // < cn: the chunk has a tile t
+        load_tile<PPT>(base, first, wg, cn, p);
+        return cn - first < (uint64_t)wg * PPT ? (uint32_t)(cn - first) : wg * PPT;
     }
 };
 
@@ -421,11 +388,9 @@ __global__ __launch_bounds__(1024) void k_basic(const u32x4 *__restrict__ pts, T
     for (uint64_t b = blockIdx.x; b < tl.nblocks; b += gridDim.x) {
         uint64_t t;
         if (!src.tile(tl, b, t)) continue;
-        const uint64_t first = t * wg * PPT;
-        // Lanes of the tile that hold a point (uniform bound; 32-bit compares).
-        const uint32_t lim = tl.n - first < (uint64_t)wg * PPT ? (uint32_t)(tl.n - first) : wg * PPT;
         u32x4 p[PPT];
-        src.template load<PPT>(pts, first, wg, tl.n, p);
+        // lim: lanes of the tile that hold a point (uniform; 32-bit compares).
+        const uint32_t lim = src.template load<PPT>(pts, t, wg, tl.n, p);
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             uint32_t dbits;
@@ -468,11 +433,9 @@ __device__ __forceinline__ void dedup_tiles(const u32x4 *__restrict__ pts, Tiles
     for (uint64_t b = blockIdx.x; b < tl.nblocks; b += gridDim.x) {
         uint64_t t;
         if (!src.tile(tl, b, t)) continue;
-        const uint64_t first = t * wg * PPT;
-        // Lanes of the tile that hold a point (uniform bound; 32-bit compares).
-        const uint32_t lim = tl.n - first < (uint64_t)wg * PPT ? (uint32_t)(tl.n - first) : wg * PPT;
         u32x4 p[PPT];
-        src.template load<PPT>(pts, first, wg, tl.n, p);
+        // lim: lanes of the tile that hold a point (uniform; 32-bit compares).
+        const uint32_t lim = src.template load<PPT>(pts, t, wg, tl.n, p);
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             uint32_t dbits;
@@ -568,11 +531,9 @@ __device__ __forceinline__ void hq_color_tiles(const u32x4 *__restrict__ pts, Ti
     for (uint64_t b = blockIdx.x; b < tl.nblocks; b += gridDim.x) {
         uint64_t t;
         if (!src.tile(tl, b, t)) continue;
-        const uint64_t first = t * wg * PPT;
-        // Lanes of the tile that hold a point (uniform bound; 32-bit compares).
-        const uint32_t lim = tl.n - first < (uint64_t)wg * PPT ? (uint32_t)(tl.n - first) : wg * PPT;
         u32x4 p[PPT];
-        src.template load<PPT>(pts, first, wg, tl.n, p);
+        // lim: lanes of the tile that hold a point (uniform; 32-bit compares).
+        const uint32_t lim = src.template load<PPT>(pts, t, wg, tl.n, p);
         // Project every point first, then read all their closest depths back
         // to back (one round trip for the tile instead of one per point).
         uint32_t pids[PPT], dbs[PPT], dref[PPT];
@@ -868,8 +829,8 @@ struct ColorL {
 
 // ---- many-chunk frames ------------------------------------------------------
 
-// Exclusive prefix of the chunk sizes into start[0..nchunks] (one workgroup;
-// a skipped chunk counts 0 points).
+// Exclusive prefix of the chunks' tile counts (tiles of T points) into
+// start[0..nchunks] (one workgroup; a skipped chunk has no tile).
 __device__ __forceinline__ uint64_t shfl_up64(uint64_t x, uint32_t d) {
     uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)x, d, 64);
     uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(x >> 32), d, 64);
@@ -877,7 +838,7 @@ __device__ __forceinline__ uint64_t shfl_up64(uint64_t x, uint32_t d) {
 }
 
 __global__ __launch_bounds__(1024) void k_chunk_starts(const pcr_chunk *__restrict__ chunks, uint32_t nchunks,
-                                                       uint64_t *__restrict__ start) {
+                                                       uint32_t T, uint64_t *__restrict__ start) {
     __shared__ uint64_t wtot[16];
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     uint64_t carry = 0;
@@ -887,7 +848,7 @@ __global__ __launch_bounds__(1024) void k_chunk_starts(const pcr_chunk *__restri
         if (i < nchunks) {
             const pcr_chunk ch = chunks[i];
             const bool ok = ch.pts != nullptr && ((uintptr_t)ch.pts & 15u) == 0 && ch.n <= PCR_CHUNK_MAX_POINTS;
-            c = ok ? ch.n : 0;
+            c = ok ? (ch.n + T - 1) / T : 0;  // tiles of the chunk
         }
         uint64_t x = c;  // inclusive scan over the wavefront
         for (uint32_t d = 1; d < 64; d <<= 1) {
@@ -1108,9 +1069,6 @@ extern "C" int pcr_render_chunks(const pcr_chunk *chunks, uint32_t nchunks, cons
     Shape sh;
     rc = resolve_shape(tune, fam, sh);
     if (rc != PCR_OK) return rc;
-    // Persistent workgroups walk the chunk table once per tile: larger tiles
-    // (256 threads) amortise that walk, unless the caller chose a size.
-    if (!tune || tune->wg == 0) sh.wg = 256;
     if (nchunks == 0) return PCR_OK;
     if (!chunks || ((uintptr_t)chunks & 7)) return fail(PCR_EINVAL, "chunks must be an 8-byte aligned device pointer");
     if (!scratch || ((uintptr_t)scratch & 15)) return fail(PCR_EINVAL, "scratch must be a 16-byte aligned device pointer");
@@ -1119,7 +1077,7 @@ extern "C" int pcr_render_chunks(const pcr_chunk *chunks, uint32_t nchunks, cons
         return fail(PCR_ENOMEM, "scratch holds %zu bytes, %u chunks need %zu", scratch_bytes, nchunks, need);
     hipStream_t s = (hipStream_t)stream;
     uint64_t *start = (uint64_t *)scratch;
-    hipLaunchKernelGGL(k_chunk_starts, dim3(1), dim3(1024), 0, s, chunks, nchunks, start);
+    hipLaunchKernelGGL(k_chunk_starts, dim3(1), dim3(1024), 0, s, chunks, nchunks, sh.wg * sh.ppt, start);
     PCR_LAUNCHED();
     uint32_t pass = flags & kHqPassMask;
     if (pass == 0) pass = kHqPassMask;
