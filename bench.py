@@ -44,10 +44,10 @@ HBM_PEAK_GBS = 8000.0
 # kernel sources they were taken on: `src` is the sha256 of the render sources.
 MEASURED_TRAFFIC = {
     # profiles/render_terrain100M_1080p.md
-    "k_basic": {"src": "4127dcfe6857eee65b9f2a9f1481aa755afb6b062ce604cce2c1adc8e3c570eb",
-                "fetch_bytes": 1600015497, "write_bytes": 1263360448},
-    "k_dedup<u64>": {"src": "4127dcfe6857eee65b9f2a9f1481aa755afb6b062ce604cce2c1adc8e3c570eb",
-                     "fetch_bytes": 1600172592, "write_bytes": 111195744},
+    "k_basic": {"src": "c78abd7c82bec2ab9193de9792fb2403b5da879eb530c7bd44a6ecf77ea95924",
+                "fetch_bytes": 1600000027, "write_bytes": 1263360448},
+    "k_dedup<u64>": {"src": "c78abd7c82bec2ab9193de9792fb2403b5da879eb530c7bd44a6ecf77ea95924",
+                     "fetch_bytes": 1600162370, "write_bytes": 111195744},
 }
 
 

@@ -111,15 +111,14 @@ enum {
 };
 
 /* Launch shape for the render kernels.  Zero fields take the defaults
- * (measured on MI355X): basic 4 points per thread in 256-thread workgroups,
- * one tile per workgroup; deduplicating and HQ 8 points per thread in
- * 64-thread (one-wavefront) workgroups with 256 LDS slots, 512 workgroups per
- * compute unit stepping over the tiles.
+ * (measured on MI355X), all with 64-thread (one-wavefront) workgroups that
+ * step over the tiles in their natural order: basic 1 point per thread and 64
+ * workgroups per compute unit; deduplicating and HQ 8 points per thread, 256
+ * LDS slots and 512 workgroups per compute unit.
  *   ppt    points per thread (1, 2, 4, 8 or 16)
  *   wg     workgroup size (64, 128, 256, 512 or 1024)
  *   grid   workgroups per launch; each takes tiles g, g + grid, ... (0 = the
- *          default above; a basic render's default is one tile of wg*ppt
- *          points per workgroup, XCD-contiguous)
+ *          default above)
  *   group  views per point pass in a batch (0 = all that fit the cache budget;
  *          1 = every view its own pass with the single-view kernels)
  *   slots  LDS hash-table slots per workgroup of the deduplicating kernels,

@@ -53,16 +53,17 @@ static bool pow2_in(uint32_t v, uint32_t lo, uint32_t hi) {
 }
 
 int resolve_shape(const pcr_tune *tune, int family, Shape &s) {
-    // Defaults (measured on MI355X): a tile of 1024 points per 256-thread
-    // workgroup for the basic kernel; for the deduplicating and HQ ones,
-    // single-wavefront workgroups with 512-point tiles and 256 LDS slots
-    // (their barriers then never wait for another wavefront).
-    // They step over the tiles in their natural order with 512 workgroups per
-    // CU, which beat one workgroup per tile on every measured order (the
-    // basic kernel keeps one tile per workgroup).
-    s.wg = family == PCR_BASIC ? 256 : 64;
-    s.ppt = family == PCR_BASIC ? 4 : 8;
-    s.grid = family == PCR_BASIC ? 0 : 512u * (uint32_t)device_cus();
+    // Defaults (measured on MI355X), all with single-wavefront workgroups
+    // stepping over the tiles in their natural order, which beat one
+    // workgroup per tile in XCD-contiguous order on every measured order:
+    // the basic kernel (family PCR_BASIC) one point per lane and 64
+    // workgroups per CU; the deduplicating and HQ kernels 512-point tiles,
+    // 256 LDS slots (their barriers never wait for another wavefront) and 512
+    // workgroups per CU.
+    const bool basic = family == PCR_BASIC;
+    s.wg = 64;
+    s.ppt = basic ? 1 : 8;
+    s.grid = (basic ? 64u : 512u) * (uint32_t)device_cus();
     s.group = 0;
     s.slots = 0;
     if (tune) {

@@ -1021,7 +1021,8 @@ extern "C" int pcr_render_ex(const pcr_point *pts, uint64_t n, const float mvp[1
     int fam = variant & 0xFF;
     uint32_t flags = (uint32_t)variant & ~0xFFu;
     Shape sh;
-    rc = resolve_shape(tune, fam, sh);
+    // A basic render through the LDS kernel takes the deduplicating shape.
+    rc = resolve_shape(tune, fam == PCR_BASIC && (flags & PCR_F_LDS) ? PCR_DEDUP : fam, sh);
     if (rc != PCR_OK) return rc;
     if (n == 0) return PCR_OK;
     Launch L{(const u32x4 *)pts, n, make_view(mvp, w, h), fb, sh, flags & ~PCR_F_PLAIN, (hipStream_t)stream};
