@@ -247,27 +247,19 @@ __global__ __launch_bounds__(kBatchWg) void k_batch_pass(const u32x4 *__restrict
         bar_lds();
     };
 
-    // Static, XCD-aware schedule (no shared queue: same-address atomics
-    // serialise at the memory-side atomic unit).  Workgroups are dispatched
-    // round-robin over the 8 XCDs; the workgroups of XCD x walk the groups in
-    // order and, inside each group, the contiguous tile range
-    // [x*per, (x+1)*per), so each XCD's L2 sees one part of a spatially
-    // ordered cloud.  The group's views are restaged only when the group
-    // changes.
-    const uint32_t nx = gridDim.x < 8u ? gridDim.x : 8u;  // tile ranges (one per XCD)
-    const uint32_t xcd = blockIdx.x % nx, lane_wg = blockIdx.x / nx;
-    const uint32_t wgs_x = (gridDim.x - xcd + nx - 1u) / nx;  // workgroups on this range
-    const uint64_t per = (ntiles + nx - 1) / nx;
-    const uint64_t t_lo = xcd * per, t_hi = t_lo + per < ntiles ? t_lo + per : ntiles;
+    // Grid-stride over the (group, tile) items in group-major order with the
+    // tiles in their natural order (no shared queue: same-address atomics
+    // serialise at the memory-side atomic unit): the workgroups resident at
+    // one time work on one window of the point order, the schedule that the
+    // single-view kernels measured fastest.  A workgroup's items stay in one
+    // group for ntiles / grid items, so its views are restaged only when the
+    // group changes.
     const uint32_t ngroups = t.h->ngroups[PASS];
+    const uint64_t nitems = (uint64_t)ngroups * ntiles;
     uint32_t cur_g = 0xFFFFFFFFu, gcount = 0;
-    for (uint64_t item = 0;; ++item) {
-        // item-th piece of work of this workgroup: (group, tile) in group-major order
-        const uint64_t span = t_hi > t_lo ? t_hi - t_lo : 0;
-        const uint64_t mine = span > lane_wg ? (span - lane_wg + wgs_x - 1) / wgs_x : 0;
-        if (mine == 0 || item >= mine * ngroups) break;  // every workgroup reaches this exit
-        const uint32_t g = (uint32_t)(item / mine);
-        const uint64_t tile = t_lo + lane_wg + (item - (uint64_t)g * mine) * wgs_x;
+    for (uint64_t item = blockIdx.x; item < nitems; item += gridDim.x) {  // uniform exit for every workgroup
+        const uint32_t g = (uint32_t)(item / ntiles);
+        const uint64_t tile = item - (uint64_t)g * ntiles;
         const uint64_t first = tile * T;
         const uint64_t rem = n - first;
         u32x4 p[PPT];
@@ -398,6 +390,15 @@ int resident_grid(const void *fn, uint32_t wg, size_t sm, uint32_t &grid) {
     return PCR_OK;
 }
 
+// Workgroups of a batched pass: the plan's grid, or as many as are resident.
+int pass_grid(const void *fn, const pcr_batch *b, size_t sm, uint32_t &grid) {
+    if (b->sh.grid) {
+        grid = b->sh.grid;
+        return PCR_OK;
+    }
+    return resident_grid(fn, b->sh.wg, sm, grid);
+}
+
 int launch_pass(pcr_batch *b, int pass, hipStream_t s) {
     // pass < 0: only raise the kernels' LDS limit (done before graph capture).
     size_t sm = batch_lds(b->hbits);
@@ -406,8 +407,8 @@ int launch_pass(pcr_batch *b, int pass, hipStream_t s) {
         if (pass < 0) {                                                                                \
             int rc = allow_lds((const void *)&k_batch_pass<P, 0>, sm);                                 \
             if (rc == PCR_OK) rc = allow_lds((const void *)&k_batch_pass<P, 1>, sm);                   \
-            if (rc == PCR_OK) rc = resident_grid((const void *)&k_batch_pass<P, 0>, b->sh.wg, sm, b->grid_pass[0]); \
-            if (rc == PCR_OK) rc = resident_grid((const void *)&k_batch_pass<P, 1>, b->sh.wg, sm, b->grid_pass[1]); \
+            if (rc == PCR_OK) rc = pass_grid((const void *)&k_batch_pass<P, 0>, b, sm, b->grid_pass[0]);     \
+            if (rc == PCR_OK) rc = pass_grid((const void *)&k_batch_pass<P, 1>, b, sm, b->grid_pass[1]);     \
             return rc;                                                                                 \
         }                                                                                              \
         if (pass)                                                                                      \
