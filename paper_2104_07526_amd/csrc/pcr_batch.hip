@@ -1,18 +1,21 @@
 // pcr_batch.hip -- batched multi-view rendering: many cameras and framebuffers
 // of one resident cloud per launch.
 //
-// A launch is one hipGraph replay of four kernels:
+// A launch is one hipGraph replay of four stages:
 //   clear   all views' buffers
 //   pass A  closest-point views (basic / dedup) and the depth pass of HQ views
 //   pass B  the colour pass of HQ views (needs every HQ depth complete)
 //   resolve all views
-// Passes A and B are persistent: workgroups take (group, tile) items from a
-// queue in group-major order, load the tile's points once and render them into
-// every view of the group, deduplicating same-pixel updates in LDS per view.
-// Views are grouped so that a group's framebuffers fit the cache budget, which
-// keeps the atomics of a pass inside a small, cache-resident working set while
-// the point stream is read once per group.  Every update is an integer min or
-// sum, so each view is bit-identical to rendering it alone.
+// In the batched form, passes A and B are one kernel each: workgroups step
+// over (group, tile) items in group-major order, load the tile's points once
+// and render them into every view of the group, deduplicating same-pixel
+// updates in a shared LDS table.  Views are grouped so that a group's
+// framebuffers fit the cache budget, which keeps the atomics of a pass inside
+// a small, cache-resident working set while the point stream is read once per
+// group.  In the per-view form (tune group 1) every view slot runs the
+// single-view passes instead, reading its view from the device table; slots a
+// launch does not use are disabled in the graph.  Every update is an integer
+// min or sum, so each view is bit-identical to rendering it alone.
 #include <algorithm>
 #include <cstddef>
 #include <cstring>
@@ -380,8 +383,9 @@ struct pcr_batch {
 namespace pcr {
 namespace {
 
-// Workgroups of a persistent pass: as many as are resident at once on the
-// device, so that no workgroup waits for another to finish its whole share.
+// Workgroups of a batched pass without a set grid: as many as are resident at
+// once on the device, so that no workgroup waits for another to finish its
+// whole share.
 int resident_grid(const void *fn, uint32_t wg, size_t sm, uint32_t &grid) {
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, (int)wg, sm);

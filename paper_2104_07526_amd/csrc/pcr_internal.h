@@ -146,15 +146,6 @@ __device__ __forceinline__ void gadd_u64(u64 *p, u64 v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Tile index of workgroup b when every workgroup takes one tile: consecutive
-// workgroups are dispatched round-robin over the 8 XCDs, so XCD x is given the
-// contiguous tile range [x*T/8, (x+1)*T/8) and each XCD's L2 sees its own part
-// of a spatially ordered cloud.
-__device__ __forceinline__ uint64_t xcd_tile(uint64_t b, uint64_t ntiles) {
-    uint64_t per = (ntiles + 7) / 8;
-    return (b % 8) * per + b / 8;
-}
-
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------

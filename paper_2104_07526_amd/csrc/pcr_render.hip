@@ -276,11 +276,12 @@ inline uint32_t lds_hbits(uint32_t T, uint32_t group) {
 // Render kernels.  One tile = wg * PPT consecutive points; lane t loads points
 // tile*T + j*wg + t (j < PPT), all loads issued before any use.
 // ---------------------------------------------------------------------------
+// Workgroup g takes tiles g, g + grid, ... (natural order: the workgroups
+// resident at one time work on one window of the point order).
 struct Tiles {
     uint64_t n, ntiles, nblocks;
-    int remap;
     __device__ __forceinline__ bool tile(uint64_t b, uint64_t &t) const {
-        t = remap ? xcd_tile(b, ntiles) : b;
+        t = b;
         return t < ntiles;
     }
 };
@@ -696,18 +697,10 @@ Tiles make_tiles(uint64_t n, const Shape &sh, uint32_t &grid) {
     tl.n = n;
     uint64_t T = (uint64_t)sh.wg * sh.ppt;
     tl.ntiles = (n + T - 1) / T;
-    if (sh.grid == 0) {
-        // One tile per workgroup, XCD-contiguous tile ranges.
-        tl.remap = 1;
-        tl.nblocks = ((tl.ntiles + 7) / 8) * 8;
-        uint64_t g = tl.nblocks;
-        grid = (uint32_t)(g > 0x7FFFFFFFull ? 0x7FFFFFFFull : g);
-    } else {
-        tl.remap = 0;
-        tl.nblocks = tl.ntiles;
-        uint64_t g = tl.ntiles < sh.grid ? tl.ntiles : sh.grid;
-        grid = (uint32_t)(g < 1 ? 1 : g);
-    }
+    tl.nblocks = tl.ntiles;
+    // sh.grid is set by resolve_shape; 0 would mean one workgroup per tile.
+    uint64_t g = sh.grid && sh.grid < tl.ntiles ? sh.grid : tl.ntiles;
+    grid = (uint32_t)(g < 1 ? 1 : (g > 0x7FFFFFFFull ? 0x7FFFFFFFull : g));
     return tl;
 }
 
