@@ -44,10 +44,10 @@ HBM_PEAK_GBS = 8000.0
 # kernel sources they were taken on: `src` is the sha256 of the render sources.
 MEASURED_TRAFFIC = {
     # profiles/render_terrain100M_1080p.md
-    "k_basic": {"src": "c78abd7c82bec2ab9193de9792fb2403b5da879eb530c7bd44a6ecf77ea95924",
-                "fetch_bytes": 1600000027, "write_bytes": 1263360448},
-    "k_dedup<u64>": {"src": "c78abd7c82bec2ab9193de9792fb2403b5da879eb530c7bd44a6ecf77ea95924",
-                     "fetch_bytes": 1600162370, "write_bytes": 111195744},
+    "k_basic": {"src": "770ac93ba96cfbc8158c80d3648412e98b3d49b33b94043ad99e3555ef93b8c8",
+                "fetch_bytes": 1599999859, "write_bytes": 1263360448},
+    "k_dedup<u64>": {"src": "770ac93ba96cfbc8158c80d3648412e98b3d49b33b94043ad99e3555ef93b8c8",
+                     "fetch_bytes": 1600161562, "write_bytes": 111195744},
 }
 
 
