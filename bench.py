@@ -44,10 +44,10 @@ HBM_PEAK_GBS = 8000.0
 # kernel sources they were taken on: `src` is the sha256 of the render sources.
 MEASURED_TRAFFIC = {
     # profiles/render_terrain100M_1080p.md
-    "k_basic": {"src": "770ac93ba96cfbc8158c80d3648412e98b3d49b33b94043ad99e3555ef93b8c8",
-                "fetch_bytes": 1599999859, "write_bytes": 1263360448},
-    "k_dedup<u64>": {"src": "770ac93ba96cfbc8158c80d3648412e98b3d49b33b94043ad99e3555ef93b8c8",
-                     "fetch_bytes": 1600161562, "write_bytes": 111195744},
+    "k_basic": {"src": "eaaa9ed1d79f9c88bdf6811d44e2ecf6eeeb65d3e4471c73a71f138cc1773529",
+                "fetch_bytes": 1659433427, "write_bytes": 1069193888},
+    "k_dedup<u64>": {"src": "eaaa9ed1d79f9c88bdf6811d44e2ecf6eeeb65d3e4471c73a71f138cc1773529",
+                     "fetch_bytes": 1600165083, "write_bytes": 111195744},
 }
 
 

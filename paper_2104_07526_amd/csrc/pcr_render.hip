@@ -386,16 +386,38 @@ __global__ __launch_bounds__(1024) void k_basic(const u32x4 *__restrict__ pts, T
                                                 u64 *__restrict__ fb, Src src) {
     const uint32_t wg = blockDim.x;
     if constexpr (Src::chunked) src.setup(tl, wg * PPT);
+    // Without the wavefront reduction (which merges neighbouring lanes), a
+    // lane takes PPT consecutive points of a flat buffer: the 64 atomics of
+    // one instruction then fall on points PPT apart, so fewer of them meet on
+    // one pixel, and a lane's run of (often same-pixel) points is spread over
+    // PPT instructions.  Same atomics, fewer collisions (measured 16-30%
+    // faster on every vertex order).
+    constexpr bool kRuns = !REDUCE && !Src::chunked;
     for (uint64_t b = blockIdx.x; b < tl.nblocks; b += gridDim.x) {
         uint64_t t;
         if (!src.tile(tl, b, t)) continue;
         u32x4 p[PPT];
-        // lim: lanes of the tile that hold a point (uniform; 32-bit compares).
-        const uint32_t lim = src.template load<PPT>(pts, t, wg, tl.n, p);
+        // lim: points of the tile (uniform; 32-bit compares).
+        uint32_t lim;
+        if constexpr (kRuns) {
+            const uint64_t first = t * wg * PPT, rem = tl.n - first;
+            lim = rem < (uint64_t)wg * PPT ? (uint32_t)rem : wg * PPT;
+            // Cached loads: the PPT loads of a run touch each line PPT times
+            // (non-temporal loads would fetch it again from HBM each time).
+            const u32x4 *tp = pts + first;
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) {
+                const uint32_t k = threadIdx.x * PPT + j;
+                p[j] = *(const __attribute__((address_space(1))) u32x4 *)(tp + (k < lim ? k : lim - 1));
+            }
+        } else {
+            lim = src.template load<PPT>(pts, t, wg, tl.n, p);
+        }
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             uint32_t dbits;
-            uint32_t pid = project_wave(v, p[j], (uint32_t)(j * wg + threadIdx.x) < lim, dbits);
+            const uint32_t k = kRuns ? threadIdx.x * PPT + j : j * wg + threadIdx.x;
+            uint32_t pid = project_wave(v, p[j], k < lim, dbits);
             u64 key = make_key(dbits, p[j].w);
             bool w = pid != kEmptyPid;
             if (REDUCE) w = wave_reduce<u64, true>(pid, key, w);
