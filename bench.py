@@ -45,9 +45,9 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {
     # profiles/render_terrain100M_1080p.md
     "k_basic": {"src": "eaaa9ed1d79f9c88bdf6811d44e2ecf6eeeb65d3e4471c73a71f138cc1773529",
-                "fetch_bytes": 1659433427, "write_bytes": 1069193888},
+                "fetch_bytes": 1659635500, "write_bytes": 1069193888},
     "k_dedup<u64>": {"src": "eaaa9ed1d79f9c88bdf6811d44e2ecf6eeeb65d3e4471c73a71f138cc1773529",
-                     "fetch_bytes": 1600165083, "write_bytes": 111195744},
+                     "fetch_bytes": 1600067652, "write_bytes": 108992512},
 }
 
 

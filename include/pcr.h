@@ -113,8 +113,8 @@ enum {
 /* Launch shape for the render kernels.  Zero fields take the defaults
  * (measured on MI355X), all with 64-thread (one-wavefront) workgroups that
  * step over the tiles in their natural order: basic 4 consecutive points per
- * thread and 64 workgroups per compute unit; deduplicating and HQ 8 points per
- * thread, 256 LDS slots and 512 workgroups per compute unit.
+ * thread and 64 workgroups per compute unit; deduplicating 4 and HQ 8 points
+ * per thread, 256 LDS slots and 512 workgroups per compute unit.
  *   ppt    points per thread (1, 2, 4, 8 or 16)
  *   wg     workgroup size (64, 128, 256, 512 or 1024)
  *   grid   workgroups per launch; each takes tiles g, g + grid, ... (0 = the

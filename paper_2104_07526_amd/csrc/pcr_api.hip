@@ -57,12 +57,12 @@ int resolve_shape(const pcr_tune *tune, int family, Shape &s) {
     // stepping over the tiles in their natural order, which beat one
     // workgroup per tile in XCD-contiguous order on every measured order:
     // the basic kernel (family PCR_BASIC) runs of 4 points per lane and 64
-    // workgroups per CU; the deduplicating and HQ kernels 512-point tiles,
-    // 256 LDS slots (their barriers never wait for another wavefront) and 512
-    // workgroups per CU.
+    // workgroups per CU; the deduplicating and HQ kernels 256 LDS slots
+    // (their barriers never wait for another wavefront), 512 workgroups per
+    // CU and tiles of 256 points (dedup) or 512 points (HQ).
     const bool basic = family == PCR_BASIC;
     s.wg = 64;
-    s.ppt = basic ? 4 : 8;
+    s.ppt = family == PCR_HQ ? 8 : 4;
     s.grid = (basic ? 64u : 512u) * (uint32_t)device_cus();
     s.group = 0;
     s.slots = 0;
