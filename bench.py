@@ -431,17 +431,20 @@ def leg_batch(args):
                        "reorder_ms": round(rms, 2)}}
 
 
-def leg_serve(args):
-    """Eight resident clouds (10M-796M points, 36.8 GB), Poisson request load
-    at fractions of the one-at-a-time service rate; continuous-batching server
-    against a one-at-a-time server on the same arrival sequence."""
-    import threading
+# Server policy of the serve leg (picked by a sweep of 150M-1000M on this
+# load): batches that stream at least this many points run one at a time, and
+# a batch holds at most this many points x views.
+SERVE_BIG_POINTS = 250_000_000
 
-    import torch
+SERVE_SIZES = [10_000_000, 50_000_000, 100_000_000, 145_000_000, 300_000_000, 400_000_000, 500_000_000,
+               796_000_000]
+
+
+def serve_clouds(args):
+    """The eight resident clouds (terrain and buildings alternating,
+    shuffled-Morton order), scaled down by --n below 100M."""
     from paper_2104_07526_amd import pcr, synth
-    from paper_2104_07526_amd.serve import GpuBackend, Request, Server, percentile
-    sizes = [10_000_000, 50_000_000, 100_000_000, 145_000_000, 300_000_000, 400_000_000, 500_000_000,
-             796_000_000]
+    sizes = SERVE_SIZES
     if args.n < 100_000_000:                         # reduced sizes for a quick run
         sizes = [max(1_000_000, s * args.n // 100_000_000) for s in sizes]
     clouds = []
@@ -453,8 +456,20 @@ def leg_serve(args):
         del pts
         clouds.append(d)
         log(f"cloud {i}: {sz} points resident ({time.perf_counter() - t0:.0f} s)")
+    return sizes, clouds
+
+
+def serve_measure(args, clouds, servers, fracs=(0.5, 0.8, 1.0, 1.25), seed=6):
+    """Poisson request load at fractions of the one-at-a-time service rate.
+    Every rate runs the one-at-a-time server and then each entry of
+    `servers` ({name: (GpuBackend kwargs, Server kwargs)}) on the same arrival
+    sequence; a sample of every server's images is checked against the
+    one-at-a-time render."""
+    import torch
+    from paper_2104_07526_amd import pcr, synth
+    from paper_2104_07526_amd.serve import GpuBackend, Request, Server, percentile
     res = [(1280, 720), (1920, 1080), (2560, 1440), (3840, 2160)]
-    rng = np.random.default_rng(6)
+    rng = np.random.default_rng(seed)
 
     def make_requests(k):
         reqs = []
@@ -486,12 +501,14 @@ def leg_serve(args):
     svc = (time.perf_counter() - t) / len(cal)
     mu = 1.0 / svc
     nreq = args.requests
-    be = GpuBackend(clouds, budget_bytes=budget, capacity=16)
+    backends = {name: GpuBackend(clouds, budget_bytes=budget, capacity=16, **bk)
+                for name, (bk, _) in servers.items()}
     rates = {}
-    for frac in (0.5, 0.8, 1.0, 1.25):
+    for frac in fracs:
         lam = frac * mu
         reqs = make_requests(nreq)
         gaps = rng.exponential(1.0 / lam, nreq)
+        pts_total = sum(pcr._npoints(clouds[r.cloud]) for r in reqs)
         # one-at-a-time server on this arrival sequence
         start = time.perf_counter() + 0.05
         arr = start + np.cumsum(gaps)
@@ -502,52 +519,65 @@ def leg_serve(args):
             plain(r)
             lat_p.append(time.perf_counter() - a)
         wall_p = time.perf_counter() - start
-        # continuous-batching server on the same sequence, driven inline by
-        # the arrival loop (no second Python thread competing for the GIL)
-        srv = Server(be, budget_bytes=budget)
-        start = time.perf_counter() + 0.05
-        arr = start + np.cumsum(gaps)
-        futs = []
-        i = 0
-        busy = True
-        while i < nreq or busy:
-            now = time.perf_counter()
-            while i < nreq and arr[i] <= now:
-                reqs[i].arrival = float(arr[i])
-                futs.append(srv.submit(reqs[i]))
-                i += 1
-            busy = srv.step()
-        out = [f.result(timeout=600) for f in futs]
-        wall_b = max(o.finished for o in out) - start
-        lat_b = [o.latency for o in out]
-        pts_total = sum(pcr._npoints(clouds[r.cloud]) for r in reqs)
-        rates[f"{frac:.2f}"] = {
-            "lambda_req_s": round(lam, 1),
-            "plain": {"p50_ms": round(1e3 * percentile(lat_p, 50), 3), "p99_ms": round(1e3 * percentile(lat_p, 99), 3),
-                      "Gpts_s": round(pts_total / wall_p / 1e9, 2)},
-            "batched": {"p50_ms": round(1e3 * percentile(lat_b, 50), 3), "p99_ms": round(1e3 * percentile(lat_b, 99), 3),
-                        "Gpts_s": round(pts_total / wall_b / 1e9, 2),
-                        "mean_batch": round(float(np.mean([o.batch_size for o in out])), 2),
-                        "failed": sum(o.status != "ok" for o in out)},
-        }
-        log(f"rate {frac}: {rates[f'{frac:.2f}']}")
-        # identity: a sample of results against the one-at-a-time render
-        chk = torch.empty(3840 * 2160, dtype=torch.int32, device="cuda")
-        same = True
-        for r, o in list(zip(reqs, out))[:: max(1, nreq // 20)]:
-            plain(r, out=chk)
-            same &= bool(torch.equal(o.image, chk[: r.w * r.h]))
-        rates[f"{frac:.2f}"]["identical_sample"] = same
-    be.close()
+        row = {"lambda_req_s": round(lam, 1),
+               "plain": {"p50_ms": round(1e3 * percentile(lat_p, 50), 3),
+                         "p99_ms": round(1e3 * percentile(lat_p, 99), 3),
+                         "Gpts_s": round(pts_total / wall_p / 1e9, 2)}}
+        for name, (_, sk) in servers.items():
+            # continuous-batching server on the same sequence, driven inline by
+            # the arrival loop (no second Python thread competing for the GIL)
+            srv = Server(backends[name], budget_bytes=budget, **sk)
+            start = time.perf_counter() + 0.05
+            arr = start + np.cumsum(gaps)
+            futs = []
+            i = 0
+            busy = True
+            while i < nreq or busy:
+                now = time.perf_counter()
+                while i < nreq and arr[i] <= now:
+                    reqs[i].arrival = float(arr[i])
+                    futs.append(srv.submit(reqs[i]))
+                    i += 1
+                busy = srv.step()
+            out = [f.result(timeout=600) for f in futs]
+            wall_b = max(o.finished for o in out) - start
+            lat_b = [o.latency for o in out]
+            # identity: a sample of results against the one-at-a-time render
+            chk = torch.empty(3840 * 2160, dtype=torch.int32, device="cuda")
+            same = True
+            for r, o in list(zip(reqs, out))[:: max(1, nreq // 20)]:
+                plain(r, out=chk)
+                same &= bool(torch.equal(o.image, chk[: r.w * r.h]))
+            row[name] = {"p50_ms": round(1e3 * percentile(lat_b, 50), 3),
+                         "p99_ms": round(1e3 * percentile(lat_b, 99), 3),
+                         "Gpts_s": round(pts_total / wall_b / 1e9, 2),
+                         "mean_batch": round(float(np.mean([o.batch_size for o in out])), 2),
+                         "failed": sum(o.status != "ok" for o in out), "identical_sample": same}
+        rates[f"{frac:.2f}"] = row
+        log(f"rate {frac}: {row}")
+    for be in backends.values():
+        be.close()
+    return svc, rates
+
+
+def leg_serve(args):
+    """Eight resident clouds (10M-796M points, 36.8 GB), Poisson request load
+    at fractions of the one-at-a-time service rate; continuous-batching server
+    against a one-at-a-time server on the same arrival sequence."""
+    sizes, clouds = serve_clouds(args)
+    svc, rates = serve_measure(args, clouds, {"batched": ({}, {"max_batch_points": SERVE_BIG_POINTS,
+                                                              "big_points": SERVE_BIG_POINTS})})
     top = rates["1.00"]
     return {"metric": METRIC, "value": top["batched"]["Gpts_s"], "unit": "Gpts/s", "n_gpus": 1,
-            "steps": nreq, "warmup": 20, "ms_per_step": round(1e3 / mu, 3), "higher_is_better": True,
+            "steps": args.requests, "warmup": 20, "ms_per_step": round(1e3 * svc, 3), "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f32+u64", "data": "synthetic",
             "config": {"workload": "8 resident clouds " + "/".join(f"{s // 1_000_000}M" for s in sizes) +
                                    "; Poisson arrivals at 0.5/0.8/1.0/1.25 x one-at-a-time rate; requests: "
                                    "random cloud, pose, 720p-4K, basic/HQ 70/30; 2 GB framebuffer budget",
-                       "requests_per_rate": nreq},
+                       "requests_per_rate": args.requests},
             "detail": {"service_ms_one_at_a_time": round(1e3 * svc, 3), "rates": rates,
+                       "server": {"streams": 8, "max_batch_points": SERVE_BIG_POINTS,
+                                  "big_points": SERVE_BIG_POINTS},
                        "p50_ms_at_1.0": top["batched"]["p50_ms"], "p99_ms_at_1.0": top["batched"]["p99_ms"]}}
 
 

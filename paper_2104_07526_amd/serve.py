@@ -2,12 +2,15 @@
 
 Requests (cloud, camera, resolution, variant) arrive at any time.  The
 scheduler admits them in arrival order while their framebuffers fit the
-framebuffer memory budget, and launches, for every cloud with admitted work
-and a free batch slot, one batched multi-view render of everything admitted
-for that cloud so far.  Each cloud has two batch plans on two streams, so a
-new batch of a cloud starts while its previous batch is still on the GPU, and
-batches of different clouds overlap on the device.  A request's image is the
-same as rendering it alone (integer min / sum updates).
+framebuffer memory budget.  Whenever a batch slot is free it launches, oldest
+waiting request first, one batched multi-view render of everything admitted
+for that request's cloud so far.  A slot is a free batch plan of the cloud
+(two per cloud, so a new batch of a cloud starts while its previous batch is
+still on the GPU) and a free stream of a small pool: batches on different
+streams overlap on the device.  Optionally, batches that stream many points
+run one at a time beside any number of small ones, and the views of one batch
+are capped by the cloud's size.  A request's image is the same as rendering it
+alone (integer min / sum updates).
 
 The scheduler is independent of the device: a backend supplies buffer sizes,
 batch launches and completion queries.  ``GpuBackend`` drives libpcr batch
@@ -95,15 +98,17 @@ class Arena:
 
 
 class GpuBackend:
-    """libpcr batch plans on torch streams.  Framebuffers are carved from one
-    device arena (the admission budget); each request's image is its own
-    device tensor, written directly by the batch's resolve.  The plans run
+    """libpcr batch plans on a pool of torch streams.  Framebuffers are carved
+    from one device arena (the admission budget); each request's image is its
+    own device tensor, written directly by the batch's resolve.  The plans run
     each view as its own single-view pass (tune group 1) unless ``tune`` says
     otherwise: on large resident clouds the per-view passes are the faster
-    form (the batched pass is compute bound)."""
+    form (the batched pass is compute bound).  At most ``streams`` batches
+    are in flight, each on a stream of its own (8 measured best of 2-16 on the
+    eight-cloud request load)."""
 
     def __init__(self, clouds, budget_bytes: int, capacity: int = 16, plans_per_cloud: int = 2,
-                 tune=None, device="cuda", min_plan_views: int = 2):
+                 tune=None, device="cuda", min_plan_views: int = 2, streams: int = 8):
         if tune is None:
             tune = {"group": 1}
         import torch
@@ -114,13 +119,11 @@ class GpuBackend:
         self.capacity = capacity
         self.arena_mem = torch.empty(budget_bytes, dtype=torch.uint8, device=device)
         self.base = self.arena_mem.data_ptr()
-        self.slots = []              # per cloud: [plan, stream, event or None]
-        for c in clouds:
-            row = []
-            for _ in range(plans_per_cloud):
-                s = torch.cuda.Stream(device=device)
-                row.append([pcr.BatchPlan(c, capacity, tune=tune, stream=s), s, None])
-            self.slots.append(row)
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(max(1, streams))]
+        self.stream_busy = [None] * len(self.streams)     # completion event of the batch on it
+        self.plans = [[pcr.BatchPlan(c, capacity, tune=tune, stream=self.streams[0])
+                       for _ in range(plans_per_cloud)] for c in clouds]
+        self.plan_busy = [[False] * plans_per_cloud for _ in clouds]
         self.points = [pcr._npoints(c) for c in clouds]
 
     def bytes_for(self, req: Request) -> int:
@@ -130,13 +133,17 @@ class GpuBackend:
         return self.torch.empty(req.w * req.h, dtype=self.torch.int32, device=self.device)
 
     def free_slot(self, cloud: int):
-        for i, sl in enumerate(self.slots[cloud]):
-            if sl[2] is None:
-                return i
-        return None
+        """(plan, stream), both free, or None."""
+        try:
+            si = self.stream_busy.index(None)
+            pi = self.plan_busy[cloud].index(False)
+        except ValueError:
+            return None
+        return pi, si
 
-    def launch(self, cloud: int, slot: int, reqs, offsets, images):
-        plan, stream, _ = self.slots[cloud][slot]
+    def launch(self, cloud: int, slot, reqs, offsets, images):
+        pi, si = slot
+        plan, stream = self.plans[cloud][pi], self.streams[si]
         for img in images:
             img.record_stream(stream)
         if len(reqs) < self.min_plan_views:
@@ -154,22 +161,23 @@ class GpuBackend:
             plan.launch(views, stream=stream)
         ev = self.torch.cuda.Event()
         ev.record(stream)
-        self.slots[cloud][slot][2] = ev
-        return (cloud, slot)
+        self.stream_busy[si] = ev
+        self.plan_busy[cloud][pi] = True
+        return (cloud, pi, si)
 
     def done(self, handle) -> bool:
-        cloud, slot = handle
-        ev = self.slots[cloud][slot][2]
+        ev = self.stream_busy[handle[2]]
         return ev is None or ev.query()
 
     def retire(self, handle):
-        cloud, slot = handle
-        self.slots[cloud][slot][2] = None
+        cloud, pi, si = handle
+        self.stream_busy[si] = None
+        self.plan_busy[cloud][pi] = False
 
     def close(self):
-        for row in self.slots:
-            for sl in row:
-                sl[0].close()
+        for row in self.plans:
+            for plan in row:
+                plan.close()
 
 
 class Server:
@@ -178,15 +186,24 @@ class Server:
     submit() may be called from any thread; results are delivered through
     futures.  With ``run_inline`` the caller drives the loop (step())."""
 
-    def __init__(self, backend, budget_bytes: int, max_batch: int | None = None, poll_s: float = 2e-5):
+    def __init__(self, backend, budget_bytes: int, max_batch: int | None = None, poll_s: float = 2e-5,
+                 max_batch_points: int | None = None, big_points: int | None = None):
         self.be = backend
         self.arena = Arena(budget_bytes)
         self.max_batch = max_batch or backend.capacity
+        # A batch completes as a whole: on a large cloud, fewer views per batch
+        # keep its first request from waiting for the others' frames.
+        self.max_batch_points = max_batch_points
+        # Batches that stream at least big_points points (an HQ view streams
+        # its cloud twice) run one at a time in arrival order, beside any
+        # number of smaller batches: a large frame is not stretched by another
+        # large frame, and small requests never wait for one.
+        self.big_points = big_points
         self.poll_s = poll_s
         self.lock = threading.Lock()
         self.incoming = []            # (request, future) not yet admitted, arrival order
         self.admitted = {}            # cloud -> list of (request, future, offset, image)
-        self.inflight = []            # (handle, [(request, future, offset, image)], launched)
+        self.inflight = []            # (handle, [(request, future, offset, image)], launched, big)
         self.next_id = 0
         self.completed = 0
         self.rejected = 0
@@ -227,14 +244,29 @@ class Server:
                 self.admitted.setdefault(req.cloud, []).append((req, fut, off, self.be.new_image(req)))
             self.incoming = keep
 
+    def _batch_limit(self, cloud: int) -> int:
+        if not self.max_batch_points:
+            return self.max_batch
+        return max(1, min(self.max_batch, self.max_batch_points // max(1, self.be.points[cloud])))
+
+    def _streamed_points(self, cloud: int, reqs) -> int:
+        return self.be.points[cloud] * sum(2 if r.variant == pcr.HQ else 1 for r in reqs)
+
     def _launch(self):
-        for cloud, items in list(self.admitted.items()):
-            if not items:
+        big_busy = any(item[3] for item in self.inflight)
+        # the cloud of the oldest waiting request first
+        waiting = sorted((items[0][0].rid, cloud) for cloud, items in self.admitted.items() if items)
+        for _, cloud in waiting:
+            items = self.admitted[cloud]
+            k = self._batch_limit(cloud)
+            take, rest = items[:k], items[k:]
+            big = (self.big_points is not None and
+                   self._streamed_points(cloud, [t[0] for t in take]) >= self.big_points)
+            if big and big_busy:
                 continue
             slot = self.be.free_slot(cloud)
             if slot is None:
                 continue
-            take, rest = items[: self.max_batch], items[self.max_batch:]
             self.admitted[cloud] = rest
             now = time.perf_counter()
             try:
@@ -246,13 +278,15 @@ class Server:
                     fut.set_result(Result(req.rid, None, req.arrival, now, time.perf_counter(), len(take),
                                           "error", str(e)))
                 continue
-            self.inflight.append((h, take, now))
+            self.inflight.append((h, take, now, big))
+            big_busy |= big
 
     def _complete(self):
         still = []
-        for h, take, launched in self.inflight:
+        for item in self.inflight:
+            h, take, launched, _ = item
             if not self.be.done(h):
-                still.append((h, take, launched))
+                still.append(item)
                 continue
             fin = time.perf_counter()
             self.be.retire(h)

@@ -32,14 +32,17 @@ def mixed_requests(k, seed):
     return out
 
 
-def test_results_equal_solo_under_load(orc, clouds):
+@pytest.mark.parametrize("streams,max_points,big", [(8, None, None), (2, 700_000, None), (16, None, None),
+                                                    (8, 700_000, 500_000)])
+def test_results_equal_solo_under_load(orc, clouds, streams, max_points, big):
     """A burst (every request admitted before the loop runs, so batches hold
     several views) followed by a trickle served by the threaded loop while
-    earlier batches are still on the device."""
+    earlier batches are still on the device; with several stream pools,
+    batches capped by points, and large batches run one at a time."""
     import torch
     host, dev = clouds
-    be = GpuBackend(dev, budget_bytes=8 << 20, capacity=6)
-    srv = Server(be, budget_bytes=8 << 20)
+    be = GpuBackend(dev, budget_bytes=8 << 20, capacity=6, streams=streams)
+    srv = Server(be, budget_bytes=8 << 20, max_batch_points=max_points, big_points=big)
     burst = mixed_requests(24, seed=21)
     futs = [srv.submit(r) for r in burst]
     srv.drain()

@@ -15,7 +15,7 @@ class OracleBackend:
     """Test backend: batches are rendered by the CPU oracle at launch and
     reported complete `delay` seconds later."""
 
-    def __init__(self, orc, clouds, capacity=4, slots=2, delay=0.002, fail_variant=None):
+    def __init__(self, orc, clouds, capacity=4, slots=2, delay=0.002, fail_variant=None, streams=None):
         self.orc = orc
         self.clouds = clouds
         self.capacity = capacity
@@ -23,7 +23,9 @@ class OracleBackend:
         self.delay = delay
         self.fail_variant = fail_variant
         self.busy = [[None] * slots for _ in clouds]
+        self.streams = streams       # batches in flight at once over all clouds (None: no limit)
         self.batches = []
+        self.launched = []           # (cloud, [rid, ...]) in launch order
 
     def bytes_for(self, req):
         return (pcr.fb_bytes(req.w, req.h, req.variant) + 255) // 256 * 256
@@ -32,6 +34,8 @@ class OracleBackend:
         return np.zeros(req.w * req.h, np.uint32)
 
     def free_slot(self, cloud):
+        if self.streams is not None and sum(b is not None for row in self.busy for b in row) >= self.streams:
+            return None
         for i, b in enumerate(self.busy[cloud]):
             if b is None:
                 return i
@@ -44,6 +48,7 @@ class OracleBackend:
             img[:] = solo(self.orc, self.clouds[cloud], r)
         self.busy[cloud][slot] = time.perf_counter() + self.delay
         self.batches.append(len(reqs))
+        self.launched.append((cloud, [r.rid for r in reqs]))
         return (cloud, slot)
 
     def done(self, h):
@@ -121,8 +126,8 @@ def test_admission_waits_for_memory_in_arrival_order(orc, clouds):
         peak = max(peak, srv.arena.used)
         for items in srv.admitted.values():
             order += [t[0].rid for t in items if t[0].rid not in order]
-        for _, take, _ in srv.inflight:
-            order += [t[0].rid for t in take if t[0].rid not in order]
+        for item in srv.inflight:
+            order += [t[0].rid for t in item[1] if t[0].rid not in order]
         time.sleep(1e-4)
     assert peak <= 2 * one
     assert order == sorted(order)
@@ -189,3 +194,59 @@ def test_threaded_loop_and_latency_stats(orc, clouds):
     lat = [r.latency for r in res]
     assert all(x > 0 for x in lat)
     assert percentile(lat, 50) <= percentile(lat, 99)
+
+
+def test_oldest_request_launches_first_across_clouds(orc, clouds):
+    """With one batch in flight at a time, batches start in the order of their
+    oldest request, whatever the cloud."""
+    be = OracleBackend(orc, clouds, capacity=8, streams=1, delay=0.01)
+    srv = Server(be, budget_bytes=1 << 26)
+    m = synth.terrain_oblique(32, 18)
+    first = srv.submit(Request(0, m, 32, 18, pcr.BASIC))
+    srv.step()                               # on the device
+    later = [srv.submit(Request(c, m, 32, 18, pcr.BASIC)) for c in (1, 0, 1, 0, 0)]
+    srv.drain()
+    heads = [min(rids) for _, rids in be.launched]
+    assert heads == sorted(heads)
+    assert [c for c, _ in be.launched] == [0, 1, 0]
+    assert all(f.result().status == "ok" for f in [first] + later)
+
+
+def test_batch_points_cap(orc, clouds):
+    """max_batch_points bounds the views of one batch by the cloud's size (at
+    least one view), and images stay equal to solo renders."""
+    be = OracleBackend(orc, clouds, capacity=8, slots=1, delay=0.01)
+    cap = 2 * len(clouds[0]) + 10
+    srv = Server(be, budget_bytes=1 << 26, max_batch_points=cap)
+    reqs = [Request(c, synth.terrain_oblique(32, 18), 32, 18, pcr.BASIC) for c in (0,) * 7 + (1,) * 7]
+    futs = [srv.submit(r) for r in reqs]
+    srv.drain()
+    per_cloud = {0: [], 1: []}
+    for c, rids in be.launched:
+        per_cloud[c].append(len(rids))
+    assert max(per_cloud[0]) == 2 and max(per_cloud[1]) == min(8, cap // len(clouds[1]))
+    for r, f in zip(reqs, futs):
+        assert np.array_equal(f.result().image, solo(orc, clouds[r.cloud], r))
+    srv2 = Server(OracleBackend(orc, clouds), budget_bytes=1 << 20, max_batch_points=1)
+    assert srv2._batch_limit(0) == 1
+
+
+def test_big_batches_run_one_at_a_time(orc, clouds):
+    """With big_points, batches streaming at least that many points never
+    overlap each other (an HQ view counts its cloud twice), while small
+    batches run beside them; every image equals its solo render."""
+    be = OracleBackend(orc, clouds, capacity=1, slots=3, delay=0.01)
+    srv = Server(be, budget_bytes=1 << 26, big_points=len(clouds[0]) + 1)
+    m = synth.terrain_oblique(32, 18)
+    reqs = ([Request(0, m, 32, 18, pcr.HQ) for _ in range(3)] + [Request(1, m, 32, 18, pcr.BASIC) for _ in range(3)]
+            + [Request(0, m, 32, 18, pcr.BASIC)])
+    futs = [srv.submit(r) for r in reqs]
+    most_big, most_small = 0, 0
+    while srv.step():
+        big = [it for it in srv.inflight if it[3]]
+        most_big = max(most_big, len(big))
+        most_small = max(most_small, len(srv.inflight) - len(big))
+        time.sleep(2e-4)
+    assert most_big == 1 and most_small >= 2
+    for r, f in zip(reqs, futs):
+        assert np.array_equal(f.result().image, solo(orc, clouds[r.cloud], r))
