@@ -238,6 +238,10 @@ __global__ __launch_bounds__(256) void k_scan_add(uint32_t *__restrict__ a, uint
 }
 
 // Stable scatter of one pass.  off = scanned histogram (global positions).
+// The tile is first put in digit order in LDS (stably: within a digit, tile
+// order), then stored from there, so that consecutive lanes store consecutive
+// addresses of one digit's run; keys and values go through the same LDS
+// buffer one after the other.
 __global__ __launch_bounds__(kSortWg) void k_sort_scatter(const uint64_t *__restrict__ kin,
                                                           const uint32_t *__restrict__ vin, uint64_t n,
                                                           uint32_t shift, uint32_t ntiles,
@@ -245,11 +249,15 @@ __global__ __launch_bounds__(kSortWg) void k_sort_scatter(const uint64_t *__rest
                                                           uint64_t *__restrict__ kout, uint32_t *__restrict__ vout) {
     __shared__ uint32_t wcnt[kWaves][256];
     __shared__ uint32_t goff[256];
+    __shared__ uint32_t tstart[256];
+    __shared__ uint32_t scan_sh[kWaves];
+    __shared__ uint64_t stage[kSortTile];
     const uint32_t wave = threadIdx.x / 64, lane = __lane_id();
     for (uint32_t w = 0; w < kWaves; ++w) wcnt[w][threadIdx.x] = 0;
     goff[threadIdx.x] = off[(uint64_t)threadIdx.x * ntiles + blockIdx.x];
     __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * kSortTile + wave * (64 * kSortIpt);
+    const uint64_t tile0 = (uint64_t)blockIdx.x * kSortTile;
+    const uint64_t base = tile0 + wave * (64 * kSortIpt);
     uint64_t k[kSortIpt];
     uint32_t v[kSortIpt], rank[kSortIpt];
 #pragma unroll
@@ -278,25 +286,51 @@ __global__ __launch_bounds__(kSortWg) void k_sort_scatter(const uint64_t *__rest
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    {
-        uint32_t run = 0;
-        for (uint32_t w = 0; w < kWaves; ++w) {
-            uint32_t c = wcnt[w][threadIdx.x];
-            wcnt[w][threadIdx.x] = run;
-            run += c;
+    // Thread t = digit t: prefix of its count over the waves (wave order is
+    // tile order), then the start of its run in the digit-ordered tile.
+    uint32_t run = 0;
+    for (uint32_t w = 0; w < kWaves; ++w) {
+        uint32_t c = wcnt[w][threadIdx.x];
+        wcnt[w][threadIdx.x] = run;
+        run += c;
+    }
+    uint32_t total;
+    tstart[threadIdx.x] = block_scan_excl(run, scan_sh, total);
+    __syncthreads();
+    const uint32_t cnt = (uint32_t)(n - tile0 < kSortTile ? n - tile0 : kSortTile);
+    uint32_t lp[kSortIpt];
+#pragma unroll
+    for (uint32_t r = 0; r < kSortIpt; ++r) {
+        uint32_t d = (uint32_t)(k[r] >> shift) & 0xFFu;
+        lp[r] = tstart[d] + wcnt[wave][d] + rank[r];
+        if (base + r * 64 + lane < n) stage[lp[r]] = k[r];
+    }
+    __syncthreads();
+    uint32_t pos[kSortIpt];
+#pragma unroll
+    for (uint32_t r = 0; r < kSortIpt; ++r) {
+        uint32_t j = threadIdx.x + r * kSortWg;
+        pos[r] = 0xFFFFFFFFu;
+        if (j < cnt) {
+            uint64_t key = stage[j];
+            uint32_t d = (uint32_t)(key >> shift) & 0xFFu;
+            uint64_t p = (uint64_t)goff[d] + (j - tstart[d]);
+            if (p < n) {  // always true for a consistent histogram
+                pos[r] = (uint32_t)p;
+                kout[p] = key;
+            }
         }
     }
     __syncthreads();
+    uint32_t *vstage = (uint32_t *)stage;
+#pragma unroll
+    for (uint32_t r = 0; r < kSortIpt; ++r)
+        if (base + r * 64 + lane < n) vstage[lp[r]] = v[r];
+    __syncthreads();
 #pragma unroll
     for (uint32_t r = 0; r < kSortIpt; ++r) {
-        uint64_t i = base + r * 64 + lane;
-        if (i >= n) continue;
-        uint32_t d = (uint32_t)(k[r] >> shift) & 0xFFu;
-        uint64_t pos = (uint64_t)goff[d] + wcnt[wave][d] + rank[r];
-        if (pos < n) {  // always true for a consistent histogram
-            kout[pos] = k[r];
-            vout[pos] = v[r];
-        }
+        uint32_t j = threadIdx.x + r * kSortWg;
+        if (pos[r] != 0xFFFFFFFFu) vout[pos[r]] = vstage[j];
     }
 }
 
