@@ -67,9 +67,11 @@ enum {
 /* Variants (low byte of `variant`).
  * PCR_BASIC  closest point per pixel by 64-bit atomicMin (Sec. 3.1).
  * PCR_DEDUP  the same image; same-pixel updates are merged inside each
- *            wavefront and workgroup before the global atomic, and the global
- *            atomic is skipped when the stored key is already smaller
- *            (Sec. 3.2-3.4).
+ *            wavefront and workgroup before the global atomic (Sec. 3.3-3.4).
+ *            Adding PCR_F_LDS | PCR_F_REDUCE | PCR_F_EARLYZ also skips the
+ *            global atomic when the stored key is already smaller (Sec. 3.2):
+ *            worth it on unordered clouds, whose tiles merge little, and a
+ *            cost on ordered ones, so the default leaves it off.
  * PCR_HQ     blended colour of the points within 1% of the closest depth of
  *            each pixel: depth pass, colour pass, integer resolve (Sec. 3.5). */
 enum { PCR_BASIC = 0, PCR_DEDUP = 1, PCR_HQ = 2 };

@@ -65,6 +65,24 @@ def test_terrain_2m_1080p(orc, variant, order):
     assert np.array_equal(img, eimg)
 
 
+@pytest.mark.parametrize("variant", [D, HQ, B | LDS | RD, D | LDS | RD | EZ, HQ | LDS | RD | EZ])
+@pytest.mark.parametrize("shape", [None, {"ppt": 16, "wg": 256}])
+def test_ordered_and_scattered_tiles(orc, variant, shape):
+    """One launch over ordered and scattered tiles: the first half of the
+    cloud in scanline order (few pixels per tile, a full table) and the
+    second half shuffled (a distinct pixel per point, table overflows), with
+    and without the early depth test; the frame equals the oracle's."""
+    pts = synth.terrain(2_000_000, seed=2)
+    half = len(pts) // 2
+    rng = np.random.default_rng(12)
+    pts = np.concatenate([pts[:half], pts[half:][rng.permutation(len(pts) - half)]])
+    m = synth.terrain_oblique(1280, 720)
+    efb, eimg = oracle_frame(orc, pts, m, 1280, 720, variant)
+    fb, img = render_frame(upload(pts), m, 1280, 720, variant, tune=shape)
+    assert_same_fb(read_fb(fb, 1280, 720, variant), efb, variant)
+    assert np.array_equal(img, eimg)
+
+
 @pytest.mark.parametrize("variant", [B, D, B | RD, HQ, HQ | LDS])
 def test_one_pixel_contention(orc, variant):
     """200k points on one view ray: maximal atomic contention on one pixel,
