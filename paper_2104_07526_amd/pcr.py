@@ -113,6 +113,26 @@ def _ptr(t):
     return t.data_ptr() if hasattr(t, "data_ptr") else int(t)
 
 
+def _fits(t, nbytes, what):
+    """Raises ValueError when tensor ``t`` is not contiguous or holds fewer than
+    ``nbytes`` bytes, before any device work is enqueued (the library takes
+    raw addresses and cannot check; a raw address is the caller's
+    responsibility)."""
+    if t is None or not hasattr(t, "numel"):
+        return
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    have = t.numel() * t.element_size()
+    if have < nbytes:
+        raise ValueError(f"{what} holds {have} bytes, {nbytes} needed")
+
+
+def _fb_fits(fb, w, h, variant):
+    need = int(lib().pcr_fb_bytes(w, h, variant & 0xFF)) if w > 0 and h > 0 else 0
+    if need:                                # 0: invalid sizes, reported by the library call
+        _fits(fb, need, "framebuffer")
+
+
 def _npoints(points):
     nb = points.numel() * points.element_size()
     if nb % 16:
@@ -162,12 +182,17 @@ def alloc_fb(w, h, variant, device="cuda"):
 
 
 def fb_clear(fb, w, h, variant, stream=None):
+    _fb_fits(fb, w, h, variant)
     _check(lib().pcr_fb_clear(_ptr(fb), w, h, variant, _stream(stream)))
 
 
 def render(points, mvp, w, h, variant, fb, tune=None, stream=None, n=None):
     """Renders the 16-byte records of ``points`` (or the first ``n``)."""
-    n = _npoints(points) if n is None else n
+    have = _npoints(points)
+    n = have if n is None else n
+    if n > have:
+        raise ValueError(f"n = {n} but the buffer holds {have} points")
+    _fb_fits(fb, w, h, variant)
     _check(lib().pcr_render_ex(_ptr(points), n, _mvp(mvp), w, h, variant, _ptr(fb), _tune(tune),
                                _stream(stream)))
 
@@ -176,6 +201,8 @@ def resolve(fb, w, h, variant, out=None, stream=None):
     import torch
     if out is None:
         out = torch.empty(w * h, dtype=torch.int32, device=fb.device)
+    _fb_fits(fb, w, h, variant)
+    _fits(out, 4 * w * h, "image")
     _check(lib().pcr_resolve(_ptr(fb), w, h, variant, _ptr(out), _stream(stream)))
     return out
 
@@ -199,6 +226,7 @@ def render_chunks(table, nchunks, mvp, w, h, variant, fb, scratch=None, tune=Non
     if scratch is None:
         scratch = torch.empty(max(chunks_scratch_bytes(nchunks), 256), dtype=torch.uint8, device=fb.device)
     nbytes = scratch.numel() * scratch.element_size()
+    _fb_fits(fb, w, h, variant)
     _check(lib().pcr_render_chunks(_ptr(table), nchunks, _mvp(mvp), w, h, variant, _ptr(fb), _ptr(scratch),
                                    nbytes, _tune(tune), _stream(stream)))
     return scratch
@@ -223,6 +251,9 @@ def resolve_depth(fb, w, h, variant, mode=DEPTH_LINEAR, a=0.0, b=0.0, empty=floa
     import torch
     if depth is None:
         depth = torch.empty(w * h, dtype=torch.float32, device=fb.device)
+    _fb_fits(fb, w, h, variant)
+    _fits(depth, 4 * w * h, "depth image")
+    _fits(rgba, 4 * w * h, "image")
     _check(lib().pcr_resolve_depth(_ptr(fb), w, h, variant, mode, a, b, empty, _ptr(rgba), _ptr(depth),
                                    _stream(stream)))
     return depth, rgba
@@ -245,12 +276,17 @@ def reorder(points, order, batch=128, seed=0, out=None, perm=None, want_perm=Tru
     if scratch is None:
         scratch = torch.empty(max(need, 1), dtype=torch.uint8, device=points.device)
     nbytes = scratch.numel() * scratch.element_size()
+    _fits(out, 16 * n, "output points")
+    if want_perm:
+        _fits(perm, 4 * n, "permutation")
     _check(lib().pcr_reorder(_ptr(points), _ptr(out), _ptr(perm) if want_perm else None, n, order,
                              batch, seed, _ptr(scratch), nbytes, _stream(stream)))
     return out, (perm if want_perm else None)
 
 
 def make_view(mvp, w, h, variant, fb, rgba_out) -> View:
+    _fb_fits(fb, w, h, variant)
+    _fits(rgba_out, 4 * w * h, "image")
     v = View()
     v.mvp[:] = [float(x) for x in np.asarray(mvp, np.float32).reshape(16)]
     v.w, v.h, v.variant = w, h, variant

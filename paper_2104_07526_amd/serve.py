@@ -184,7 +184,8 @@ class Server:
     """Continuous-batching scheduler (see the module docstring).
 
     submit() may be called from any thread; results are delivered through
-    futures.  With ``run_inline`` the caller drives the loop (step())."""
+    futures.  start() runs the loop in a thread of its own; without it the
+    caller drives the loop with step() or drain()."""
 
     def __init__(self, backend, budget_bytes: int, max_batch: int | None = None, poll_s: float = 2e-5,
                  max_batch_points: int | None = None, big_points: int | None = None):

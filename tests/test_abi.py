@@ -6,6 +6,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 from paper_2104_07526_amd import pcr
@@ -144,3 +145,37 @@ def test_batch_argument_checks():
     assert "workgroup" in L.pcr_last_error().decode()
     assert L.pcr_batch_launch(None, None, 0, None) == pcr.EINVAL
     assert L.pcr_batch_destroy(None) == pcr.OK
+
+
+def test_binding_checks_tensor_sizes_before_enqueueing():
+    """The binding refuses tensors too small (or not contiguous) for the
+    buffers the library would write, before any call reaches the device."""
+    import torch
+    W, H = 64, 32
+    m = np.eye(4, dtype=np.float32)
+    pts = torch.zeros(100, 4, dtype=torch.int32)
+    small_fb = torch.zeros(pcr.fb_bytes(W, H, pcr.BASIC) // 8 - 1, dtype=torch.int64)
+    with pytest.raises(ValueError, match="framebuffer"):
+        pcr.fb_clear(small_fb, W, H, pcr.BASIC)
+    with pytest.raises(ValueError, match="framebuffer"):
+        pcr.render(pts, m, W, H, pcr.DEDUP | pcr.F_EARLYZ, small_fb)
+    hq_fb = torch.zeros(pcr.fb_bytes(W, H, pcr.BASIC) // 8, dtype=torch.int64)   # basic-sized, HQ needs more
+    with pytest.raises(ValueError, match="framebuffer"):
+        pcr.resolve(hq_fb, W, H, pcr.HQ, out=torch.zeros(W * H, dtype=torch.int32))
+    fb = torch.zeros(pcr.fb_bytes(W, H, pcr.BASIC) // 8, dtype=torch.int64)
+    with pytest.raises(ValueError, match="points"):
+        pcr.render(pts, m, W, H, pcr.BASIC, fb, n=101)
+    with pytest.raises(ValueError, match="image"):
+        pcr.resolve(fb, W, H, pcr.BASIC, out=torch.zeros(W * H - 1, dtype=torch.int32))
+    with pytest.raises(ValueError, match="contiguous"):
+        pcr.resolve(fb, W, H, pcr.BASIC, out=torch.zeros(W * H, 2, dtype=torch.int32)[:, 0])
+    with pytest.raises(ValueError, match="depth image"):
+        pcr.resolve_depth(fb, W, H, pcr.BASIC, depth=torch.zeros(W * H - 1, dtype=torch.float32))
+    with pytest.raises(ValueError, match="output points"):
+        pcr.reorder(pts, pcr.ORDER_MORTON, out=torch.zeros(99, 4, dtype=torch.int32), want_perm=False,
+                    scratch=torch.zeros(1 << 20, dtype=torch.uint8))
+    with pytest.raises(ValueError, match="permutation"):
+        pcr.reorder(pts, pcr.ORDER_MORTON, perm=torch.zeros(99, dtype=torch.int32),
+                    scratch=torch.zeros(1 << 20, dtype=torch.uint8))
+    with pytest.raises(ValueError, match="image"):
+        pcr.make_view(m, W, H, pcr.BASIC, fb, torch.zeros(W * H - 1, dtype=torch.int32))
