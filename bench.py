@@ -26,6 +26,7 @@ Other legs (one JSON line each, not part of the default run):
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -432,10 +433,13 @@ def leg_batch(args):
                        "reorder_ms": round(rms, 2)}}
 
 
-# Server policy of the serve leg (picked by a sweep of 150M-1000M on this
-# load): batches that stream at least this many points run one at a time, and
-# a batch holds at most this many points x views.
+# Server policy of the serve leg (picked by sweeps on this load): batches that
+# stream at least SERVE_BIG_POINTS points run one at a time (150M-1000M
+# swept), a batch holds at most that many points x views, and at most
+# SERVE_SMALL_BESIDE_BIG smaller batches run beside a large one (0, 2, 4 and
+# no limit swept).
 SERVE_BIG_POINTS = 250_000_000
+SERVE_SMALL_BESIDE_BIG = 2
 
 SERVE_SIZES = [10_000_000, 50_000_000, 100_000_000, 145_000_000, 300_000_000, 400_000_000, 500_000_000,
                796_000_000]
@@ -502,8 +506,13 @@ def serve_measure(args, clouds, servers, fracs=(0.5, 0.8, 1.0, 1.25), seed=6):
     svc = (time.perf_counter() - t) / len(cal)
     mu = 1.0 / svc
     nreq = args.requests
-    backends = {name: GpuBackend(clouds, budget_bytes=budget, capacity=16, **bk)
+    backends = {name: GpuBackend(clouds, **{"budget_bytes": budget, "capacity": 16, **bk})
                 for name, (bk, _) in servers.items()}
+    # Keep the garbage collector out of the timed loops (both servers): the
+    # objects created so far are frozen, and collection is paused meanwhile.
+    gc.collect()
+    gc.freeze()
+    gc.disable()
     rates = {}
     for frac in fracs:
         lam = frac * mu
@@ -527,7 +536,7 @@ def serve_measure(args, clouds, servers, fracs=(0.5, 0.8, 1.0, 1.25), seed=6):
         for name, (_, sk) in servers.items():
             # continuous-batching server on the same sequence, driven inline by
             # the arrival loop (no second Python thread competing for the GIL)
-            srv = Server(backends[name], budget_bytes=budget, **sk)
+            srv = Server(backends[name], budget_bytes=backends[name].arena_mem.numel(), **sk)
             start = time.perf_counter() + 0.05
             arr = start + np.cumsum(gaps)
             futs = []
@@ -556,6 +565,8 @@ def serve_measure(args, clouds, servers, fracs=(0.5, 0.8, 1.0, 1.25), seed=6):
                          "failed": sum(o.status != "ok" for o in out), "identical_sample": same}
         rates[f"{frac:.2f}"] = row
         log(f"rate {frac}: {row}")
+    gc.enable()
+    gc.unfreeze()
     for be in backends.values():
         be.close()
     return svc, rates
@@ -566,19 +577,24 @@ def leg_serve(args):
     at fractions of the one-at-a-time service rate; continuous-batching server
     against a one-at-a-time server on the same arrival sequence."""
     sizes, clouds = serve_clouds(args)
-    svc, rates = serve_measure(args, clouds, {"batched": ({}, {"max_batch_points": SERVE_BIG_POINTS,
-                                                              "big_points": SERVE_BIG_POINTS})})
+    policy = {"max_batch_points": SERVE_BIG_POINTS, "big_points": SERVE_BIG_POINTS,
+              "small_beside_big": SERVE_SMALL_BESIDE_BIG}
+    svc, rates = serve_measure(args, clouds, {"batched": ({}, policy)})
+    # framebuffer budget sweep at the one-at-a-time rate (same policy)
+    _, sweep = serve_measure(args, clouds, {f"budget_{b >> 20}MB": ({"budget_bytes": b}, policy)
+                                            for b in (512 << 20, 8 << 30)}, fracs=(1.0,), seed=7)
     top = rates["1.00"]
     return {"metric": METRIC, "value": top["batched"]["Gpts_s"], "unit": "Gpts/s", "n_gpus": 1,
             "steps": args.requests, "warmup": 20, "ms_per_step": round(1e3 * svc, 3), "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f32+u64", "data": "synthetic",
             "config": {"workload": "8 resident clouds " + "/".join(f"{s // 1_000_000}M" for s in sizes) +
                                    "; Poisson arrivals at 0.5/0.8/1.0/1.25 x one-at-a-time rate; requests: "
-                                   "random cloud, pose, 720p-4K, basic/HQ 70/30; 2 GB framebuffer budget",
+                                   "random cloud, pose, 720p-4K, basic/HQ 70/30; 2 GB framebuffer budget (0.5 GB and "
+                                   "8 GB at the one-at-a-time rate in the detail)",
                        "requests_per_rate": args.requests},
             "detail": {"service_ms_one_at_a_time": round(1e3 * svc, 3), "rates": rates,
-                       "server": {"streams": 8, "max_batch_points": SERVE_BIG_POINTS,
-                                  "big_points": SERVE_BIG_POINTS},
+                       "budget_sweep_at_1.0": sweep["1.00"],
+                       "server": {"streams": 8, **policy},
                        "p50_ms_at_1.0": top["batched"]["p50_ms"], "p99_ms_at_1.0": top["batched"]["p99_ms"]}}
 
 
@@ -834,7 +850,7 @@ def main():
     ap.add_argument("--leg", default="main", choices=["main", "hq", "big", "batch", "serve", "calib", "lod",
                                                         "resolve", "techniques"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--requests", type=int, default=600, help="requests per arrival rate (serve leg)")
+    ap.add_argument("--requests", type=int, default=2000, help="requests per arrival rate (serve leg)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the renderer runs on a single MI355X here "

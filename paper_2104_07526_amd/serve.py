@@ -188,7 +188,8 @@ class Server:
     caller drives the loop with step() or drain()."""
 
     def __init__(self, backend, budget_bytes: int, max_batch: int | None = None, poll_s: float = 2e-5,
-                 max_batch_points: int | None = None, big_points: int | None = None):
+                 max_batch_points: int | None = None, big_points: int | None = None,
+                 small_beside_big: int | None = None):
         self.be = backend
         self.arena = Arena(budget_bytes)
         self.max_batch = max_batch or backend.capacity
@@ -200,6 +201,9 @@ class Server:
         # number of smaller batches: a large frame is not stretched by another
         # large frame, and small requests never wait for one.
         self.big_points = big_points
+        # At most this many smaller batches in flight while a large one runs
+        # (None: no limit): each of them takes a share of the device from it.
+        self.small_beside_big = small_beside_big
         self.poll_s = poll_s
         self.lock = threading.Lock()
         self.incoming = []            # (request, future) not yet admitted, arrival order
@@ -255,6 +259,7 @@ class Server:
 
     def _launch(self):
         big_busy = any(item[3] for item in self.inflight)
+        small = len(self.inflight) - sum(1 for item in self.inflight if item[3])
         # the cloud of the oldest waiting request first
         waiting = sorted((items[0][0].rid, cloud) for cloud, items in self.admitted.items() if items)
         for _, cloud in waiting:
@@ -264,6 +269,9 @@ class Server:
             big = (self.big_points is not None and
                    self._streamed_points(cloud, [t[0] for t in take]) >= self.big_points)
             if big and big_busy:
+                continue
+            if (not big and big_busy and self.small_beside_big is not None
+                    and small >= self.small_beside_big):
                 continue
             slot = self.be.free_slot(cloud)
             if slot is None:
@@ -281,6 +289,7 @@ class Server:
                 continue
             self.inflight.append((h, take, now, big))
             big_busy |= big
+            small += not big
 
     def _complete(self):
         still = []

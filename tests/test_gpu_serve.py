@@ -32,17 +32,19 @@ def mixed_requests(k, seed):
     return out
 
 
-@pytest.mark.parametrize("streams,max_points,big", [(8, None, None), (2, 700_000, None), (16, None, None),
-                                                    (8, 700_000, 500_000)])
-def test_results_equal_solo_under_load(orc, clouds, streams, max_points, big):
+@pytest.mark.parametrize("streams,max_points,big,beside", [(8, None, None, None), (2, 700_000, None, None),
+                                                           (16, None, None, None), (8, 700_000, 500_000, None),
+                                                           (8, 700_000, 500_000, 1)])
+def test_results_equal_solo_under_load(orc, clouds, streams, max_points, big, beside):
     """A burst (every request admitted before the loop runs, so batches hold
     several views) followed by a trickle served by the threaded loop while
     earlier batches are still on the device; with several stream pools,
-    batches capped by points, and large batches run one at a time."""
+    batches capped by points, large batches run one at a time, and few small
+    batches beside a large one."""
     import torch
     host, dev = clouds
     be = GpuBackend(dev, budget_bytes=8 << 20, capacity=6, streams=streams)
-    srv = Server(be, budget_bytes=8 << 20, max_batch_points=max_points, big_points=big)
+    srv = Server(be, budget_bytes=8 << 20, max_batch_points=max_points, big_points=big, small_beside_big=beside)
     burst = mixed_requests(24, seed=21)
     futs = [srv.submit(r) for r in burst]
     srv.drain()

@@ -250,3 +250,24 @@ def test_big_batches_run_one_at_a_time(orc, clouds):
     assert most_big == 1 and most_small >= 2
     for r, f in zip(reqs, futs):
         assert np.array_equal(f.result().image, solo(orc, clouds[r.cloud], r))
+
+
+def test_small_batches_beside_a_big_one_are_capped(orc, clouds):
+    """small_beside_big bounds the smaller batches in flight while a big one
+    runs; without a big batch they are not limited."""
+    be = OracleBackend(orc, clouds, capacity=1, slots=8, delay=0.01)
+    srv = Server(be, budget_bytes=1 << 26, big_points=len(clouds[0]) + 1, small_beside_big=1)
+    m = synth.terrain_oblique(32, 18)
+    reqs = [Request(0, m, 32, 18, pcr.HQ)] + [Request(1, m, 32, 18, pcr.BASIC) for _ in range(6)]
+    futs = [srv.submit(r) for r in reqs]
+    most_small_with_big, most_small = 0, 0
+    while srv.step():
+        big = sum(1 for it in srv.inflight if it[3])
+        small = len(srv.inflight) - big
+        if big:
+            most_small_with_big = max(most_small_with_big, small)
+        most_small = max(most_small, small)
+        time.sleep(2e-4)
+    assert most_small_with_big == 1 and most_small > 1
+    for r, f in zip(reqs, futs):
+        assert np.array_equal(f.result().image, solo(orc, clouds[r.cloud], r))
