@@ -236,8 +236,11 @@ __global__ __launch_bounds__(kBatchWg) void k_batch_pass(const u32x4 *__restrict
             S.val[2 * h + 1] = 0ull;
             if (PASS == 0) {
                 if (vhq[vs]) {
+                    // Early test: any value the word has held is >= its
+                    // current one, so a stale read never skips a needed update.
                     uint32_t *D = (uint32_t *)vbuf[vs][0];
-                    if ((uint32_t)a < D[pid]) gmin_u32(D + pid, (uint32_t)a);
+                    const uint32_t seen = __hip_atomic_load(D + pid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if ((uint32_t)a < seen) gmin_u32(D + pid, (uint32_t)a);
                 } else {
                     gmin_u64((u64 *)vbuf[vs][0] + pid, a);
                 }
