@@ -46,10 +46,10 @@ HBM_PEAK_GBS = 8000.0
 # kernel sources they were taken on: `src` is the sha256 of the render sources.
 MEASURED_TRAFFIC = {
     # profiles/render_terrain100M_1080p.md
-    "k_basic": {"src": "eaaa9ed1d79f9c88bdf6811d44e2ecf6eeeb65d3e4471c73a71f138cc1773529",
-                "fetch_bytes": 1659635500, "write_bytes": 1069193888},
-    "k_dedup<u64>": {"src": "eaaa9ed1d79f9c88bdf6811d44e2ecf6eeeb65d3e4471c73a71f138cc1773529",
-                     "fetch_bytes": 1600067652, "write_bytes": 108992512},
+    "k_basic": {"src": "5938d338d60223fa0e85b252e20127109baed0043eadf1ec679542ccda1e61fe",
+                "fetch_bytes": 1670933501, "write_bytes": 1069193888},
+    "k_dedup<u64>": {"src": "5938d338d60223fa0e85b252e20127109baed0043eadf1ec679542ccda1e61fe",
+                     "fetch_bytes": 1600076082, "write_bytes": 108992512},
 }
 
 

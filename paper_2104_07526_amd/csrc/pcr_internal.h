@@ -91,13 +91,16 @@ __device__ __forceinline__ uint32_t finish(const View &v, const Clip &c, uint32_
     float rw = recip_rn(c.cw);
     float fx = (c.cx * rw + 1.0f) * v.hw;
     float fy = (c.cy * rw + 1.0f) * v.hh;
-    bool ok = (c.cw > 0.0f) && (fx >= 0.0f) && (fx < v.fW) && (fy >= 0.0f) && (fy < v.fH);
+    // Bitwise '&' (the tests have no side effects): evaluated without
+    // branches, where '&&' made the compiler diverge on every point.
+    bool ok = (c.cw > 0.0f) & (fx >= 0.0f) & (fx < v.fW) & (fy >= 0.0f) & (fy < v.fH);
     dbits = __float_as_uint(c.cw);
     uint32_t px = (uint32_t)(ok ? fx : 0.0f);
     uint32_t py = (uint32_t)(ok ? fy : 0.0f);
     // py < H and W are below 2^24 and W*H below 2^32; __umul24 returns the
     // low 32 bits of the product as a signed int, taken back as unsigned.
-    return ok ? (uint32_t)__umul24(py, v.W) + px : kEmptyPid;
+    const uint32_t pid = (uint32_t)__umul24(py, v.W) + px;
+    return ok ? pid : kEmptyPid;
 }
 
 __device__ __forceinline__ uint32_t project(const View &v, float x, float y, float z,

@@ -567,7 +567,9 @@ __device__ __forceinline__ void hq_color_tiles(const u32x4 *__restrict__ pts, Ti
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             const uint32_t pid = pids[j];
-            bool live = pid != kEmptyPid && __uint_as_float(dbs[j]) <= __uint_as_float(dref[j]) * 1.01f;
+            // branch-free '&': for an empty pixel dref is pixel 0's depth and the
+            // result is false either way
+            bool live = (pid != kEmptyPid) & (__uint_as_float(dbs[j]) <= __uint_as_float(dref[j]) * 1.01f);
             u64 r = p[j].w & 0xFFu, g = (p[j].w >> 8) & 0xFFu, bl = (p[j].w >> 16) & 0xFFu;
             u64 rg = (r << 32) | g, ba = (bl << 32) | 1u;
             wave_group_sums(pid, p[j].w, rg, ba, live);
