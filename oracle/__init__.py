@@ -61,6 +61,8 @@ def _declare(lib):
         "oracle_render_hq_color": (None, [P, U64, P, U32, U32, P, P, P]),
         "oracle_render_hq": (None, [P, U64, P, U32, U32, P, P, P]),
         "oracle_resolve_hq": (None, [P, P, U32, U32, P]),
+        "oracle_render_hq_packed_color": (None, [P, U64, P, U32, U32, P, P]),
+        "oracle_resolve_hq_packed": (None, [P, U32, U32, P]),
         "oracle_resolve_depth_basic": (None, [P, U32, U32, I32, F, F, F, P]),
         "oracle_resolve_depth_hq": (None, [P, U32, U32, I32, F, F, F, P]),
         "oracle_splitmix64": (U64, [U64, U64]),
@@ -190,6 +192,28 @@ class Oracle:
         BA = np.ascontiguousarray(BA, dtype=np.uint64)
         out = np.empty(W * H, np.uint32)
         self.lib.oracle_resolve_hq(_ptr(RG), _ptr(BA), W, H, _ptr(out))
+        return out
+
+    def render_hq_packed(self, points, m, W, H, D=None, P=None, passes="both"):
+        """(D, P) of the single-atomic HQ form: the depth pass as render_hq,
+        then one packed 18-18-18-10 word per pixel (Sec. 3.5.1)."""
+        if D is None:
+            D = np.full(W * H, 0xFFFFFFFF, np.uint32)
+        if P is None:
+            P = np.zeros(W * H, np.uint64)
+        p = _pts(points)
+        m = _mvp(m)
+        n = _n(p)
+        if passes in ("both", "depth"):
+            self.lib.oracle_render_hq_depth(_ptr(p), n, _ptr(m), W, H, _ptr(D))
+        if passes in ("both", "color"):
+            self.lib.oracle_render_hq_packed_color(_ptr(p), n, _ptr(m), W, H, _ptr(D), _ptr(P))
+        return D, P
+
+    def resolve_hq_packed(self, P, W, H):
+        P = np.ascontiguousarray(P, dtype=np.uint64)
+        out = np.empty(W * H, np.uint32)
+        self.lib.oracle_resolve_hq_packed(_ptr(P), W, H, _ptr(out))
         return out
 
     def resolve_depth_basic(self, fb, W, H, mode=0, a=0.0, b=0.0, empty=float("inf")):

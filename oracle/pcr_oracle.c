@@ -201,6 +201,51 @@ void oracle_resolve_hq(const uint64_t *RG, const uint64_t *BA, uint32_t W, uint3
     }
 }
 
+/* ---- single-atomic HQ colour sums (Sec. 3.5.1, the 18-18-18-10 form) ---
+ * Red, green and blue sums in 18 bits each and the count in 10 bits of one
+ * 64-bit word per pixel.  Reading of the field order, which the paper leaves
+ * open for this form: red highest, the count lowest, as in its 16-16-16-16
+ * listing: word = r << 46 | g << 28 | b << 10 | count.  Every contributing
+ * point adds its packed value modulo 2^64, so a field that passes its width
+ * carries into the next one up; the sums are exact while at most 1023 points
+ * blend into one pixel (255 * 1023 < 2^18).  Depth pass and threshold as in
+ * oracle_render_hq_color. */
+void oracle_render_hq_packed_color(const struct opoint *pts, uint64_t n, const float *m,
+                                   uint32_t W, uint32_t H, const uint32_t *D, uint64_t *P)
+{
+    for (uint64_t i = 0; i < n; ++i) {
+        uint32_t pid, dbits;
+        if (!oracle_project(m, W, H, pts[i].x, pts[i].y, pts[i].z, &pid, &dbits))
+            continue;
+        float depth = u2f(dbits);
+        float limit = u2f(D[pid]) * 1.01f;
+        if (depth <= limit) {
+            uint64_t r = pts[i].rgba & 0xFFu;
+            uint64_t g = (pts[i].rgba >> 8) & 0xFFu;
+            uint64_t b = (pts[i].rgba >> 16) & 0xFFu;
+            P[pid] += (r << 46) | (g << 28) | (b << 10) | 1u;
+        }
+    }
+}
+
+/* Resolve of the packed word: the count is its low 10 bits; each channel its
+ * 18-bit field divided by the count (truncating); alpha 255; count 0 -> 0. */
+void oracle_resolve_hq_packed(const uint64_t *P, uint32_t W, uint32_t H, uint32_t *out)
+{
+    for (uint64_t p = 0; p < (uint64_t)W * H; ++p) {
+        uint64_t a = P[p] & 0x3FFull;
+        if (a == 0) {
+            out[p] = 0;
+            continue;
+        }
+        uint64_t r = ((P[p] >> 46) & 0x3FFFFull) / a;
+        uint64_t g = ((P[p] >> 28) & 0x3FFFFull) / a;
+        uint64_t b = ((P[p] >> 10) & 0x3FFFFull) / a;
+        out[p] = (uint32_t)(r & 0xFFu) | (uint32_t)(g & 0xFFu) << 8 |
+                 (uint32_t)(b & 0xFFu) << 16 | 0xFF000000u;
+    }
+}
+
 /* ---- depth output of the resolve (Sec. 3.1, closing paragraph) --------- */
 
 /* The stored depth is the linear depth w itself.  For hybrid rendering the

@@ -583,6 +583,87 @@ def check_depth_hq_equals_basic(orc):
         assert np.any(x == -2.0) and np.any(x != -2.0)
 
 
+# ---------------------------------------------------------------------------
+# Single-atomic HQ form (Sec. 3.5.1: 18-bit colour sums and a 10-bit count in
+# one 64-bit word; field order r, g, b, count from the top is this project's
+# reading)
+# ---------------------------------------------------------------------------
+
+def _packed(r, g, b):
+    return (r << 46) | (g << 28) | (b << 10) | 1
+
+
+def _resolve_packed_by_hand(word):
+    a = word & 0x3FF
+    if a == 0:
+        return 0
+    r, g, b = (word >> 46) & 0x3FFFF, (word >> 28) & 0x3FFFF, (word >> 10) & 0x3FFFF
+    return (r // a & 255) | (g // a & 255) << 8 | (b // a & 255) << 16 | 0xFF000000
+
+
+def check_hq_packed_matches_two_words(orc):
+    """With at most 1023 points per pixel the packed word holds exactly the
+    two-word sums (count, red, green, blue) and resolves to the same image."""
+    rng = np.random.default_rng(31)
+    W, H = 48, 32
+    m = synth.mvp((0.0, 0.0, 4.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), W, H, fovy=50.0)
+    xyz = rng.uniform(-1.6, 1.6, (30_000, 3))
+    xyz[10_000:20_000] = xyz[:10_000]                   # equal depths: several points blend
+    pts = make_points(xyz, rng.integers(0, 2**32, len(xyz), dtype=np.uint64).astype(np.uint32))
+    D, RG, BA = orc.render_hq(pts, m, W, H)
+    D2, P = orc.render_hq_packed(pts, m, W, H)
+    assert np.array_equal(D, D2)
+    cnt = BA & np.uint64(0xFFFFFFFF)
+    assert int(cnt.max()) <= 1023 and int(cnt.max()) >= 2
+    assert np.array_equal(P & np.uint64(0x3FF), cnt)
+    assert np.array_equal((P >> np.uint64(46)) & np.uint64(0x3FFFF), RG >> np.uint64(32))
+    assert np.array_equal((P >> np.uint64(28)) & np.uint64(0x3FFFF), RG & np.uint64(0xFFFFFFFF))
+    assert np.array_equal((P >> np.uint64(10)) & np.uint64(0x3FFFF), BA >> np.uint64(32))
+    assert np.array_equal(orc.resolve_hq_packed(P, W, H), orc.resolve_hq(RG, BA, W, H))
+
+
+def check_hq_packed_overflow(orc):
+    """Points at one pixel and one depth: the packed word is the sum of the
+    per-point packed values modulo 2^64 (computed here with Python integers),
+    and the resolve follows by hand.  1023 points are exact; 1024 wrap the
+    count to 0 (the pixel resolves empty, the paper's artifact); 1025 carry
+    one into the blue field."""
+    W, H = 8, 8
+    m = identity(m14=1.0, m15=0.0)   # clip w = z, pixel (4,4) for x = y = 0
+    p = 4 * W + 4
+    rng = np.random.default_rng(32)
+    for k in (1, 2, 1023, 1024, 1025, 2100):
+        cols = rng.integers(0, 256, (k, 3))
+        cols[: k // 2] = 255                              # drive the fields towards their width
+        rgba = [int(synth.pack_rgba(int(r), int(g), int(b))) for r, g, b in cols]
+        D, P = orc.render_hq_packed(make_points([(0, 0, 2.0)] * k, rgba), m, W, H)
+        want = sum(_packed(int(r), int(g), int(b)) for r, g, b in cols) % (1 << 64)
+        assert int(P[p]) == want, (k, hex(int(P[p])), hex(want))
+        assert np.count_nonzero(P) == 1
+        img = orc.resolve_hq_packed(P, W, H)
+        assert int(img[p]) == _resolve_packed_by_hand(want), k
+        if k <= 1023:
+            sums = cols.sum(axis=0)
+            assert int(img[p]) == int(synth.pack_rgba(*(int(x) // k for x in sums)))
+        if k == 1024:
+            assert int(img[p]) == 0
+    # The threshold is inclusive here too: a point exactly at fl32(closest *
+    # 1.01f) counts, the next float above does not.
+    thr = np.float32(2.0) * np.float32(1.01)
+    above = np.nextafter(thr, np.float32(np.inf), dtype=np.float32)
+    for z, count in ((float(thr), 2), (float(above), 1)):
+        _, P = orc.render_hq_packed(make_points([(0, 0, 2.0), (0, 0, z)], [0, 0]), m, W, H)
+        assert int(P[p]) & 0x3FF == count, (z, int(P[p]))
+
+
+def check_resolve_hq_packed(orc):
+    words = [0, _packed(9, 18, 27), _packed(255, 0, 7) + _packed(1, 2, 3) + _packed(100, 50, 25),
+             (5 << 46) | (6 << 28) | (7 << 10)]          # sums without a count: empty
+    out = orc.resolve_hq_packed(np.array(words, np.uint64), 2, 2)
+    assert out.tolist() == [0, 9 | 18 << 8 | 27 << 16 | 0xFF000000,
+                            (356 // 3) | (52 // 3) << 8 | (35 // 3) << 16 | 0xFF000000, 0]
+
+
 ALL_CHECKS = [
     check_hand_cases, check_projection_fp64, check_projection_dyadic, check_projection_rounding,
     check_basic_brute_force, check_basic_permutation, check_basic_accumulate,
@@ -592,4 +673,5 @@ ALL_CHECKS = [
     check_splitmix64, check_morton_interleave, check_morton_quantisation, check_reorder,
     check_reorder_edges, check_image_order_invariance,
     check_depth_linear, check_depth_window, check_depth_dyadic, check_depth_hq_equals_basic,
+    check_hq_packed_matches_two_words, check_hq_packed_overflow, check_resolve_hq_packed,
 ]

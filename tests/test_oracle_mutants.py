@@ -58,6 +58,14 @@ MUTANTS = [
      []),
     ("uncovered depth 0", [("out[p] = empty;", "out[p] = 0.0f;")], []),
     ("hq depth empty test on 0", [("D[p] == 0xFFFFFFFFu ? empty", "D[p] == 0u ? empty")], []),
+    ("packed green field at 27", [("(r << 46) | (g << 28) | (b << 10) | 1u", "(r << 46) | (g << 27) | (b << 10) | 1u")],
+     []),
+    ("packed count of 9 bits", [("uint64_t a = P[p] & 0x3FFull;", "uint64_t a = P[p] & 0x1FFull;")], []),
+    ("packed red and blue swapped", [("(r << 46) | (g << 28) | (b << 10) | 1u", "(b << 46) | (g << 28) | (r << 10) | 1u")],
+     []),
+    ("packed red field of 17 bits", [("((P[p] >> 46) & 0x3FFFFull)", "((P[p] >> 46) & 0x1FFFFull)")], []),
+    ("packed threshold strict", [("        if (depth <= limit) {\n            uint64_t r = pts[i].rgba & 0xFFu;\n            uint64_t g = (pts[i].rgba >> 8) & 0xFFu;\n            uint64_t b = (pts[i].rgba >> 16) & 0xFFu;\n            P[pid]",
+                                  "        if (depth < limit) {\n            uint64_t r = pts[i].rgba & 0xFFu;\n            uint64_t g = (pts[i].rgba >> 8) & 0xFFu;\n            uint64_t b = (pts[i].rgba >> 16) & 0xFFu;\n            P[pid]")], []),
 ]
 
 
