@@ -289,8 +289,9 @@ def leg_hq(args):
     d, rms = upload_reordered(pts, pcr.ORDER_MORTON_SHUFFLE)
     del pts
     img = torch.empty(W * H, dtype=torch.int32, device="cuda")
-    out = {}
-    for name, var in (("hq", pcr.HQ), ("hq_plain", pcr.HQ | pcr.F_PLAIN), ("dedup", pcr.DEDUP),
+    out, images = {}, {}
+    for name, var in (("hq", pcr.HQ), ("hq_plain", pcr.HQ | pcr.F_PLAIN), ("hq_packed", pcr.HQ | pcr.F_HQ_PACKED),
+                      ("hq_packed_plain", pcr.HQ | pcr.F_HQ_PACKED | pcr.F_PLAIN), ("dedup", pcr.DEDUP),
                       ("basic", pcr.BASIC)):
         fb = pcr.alloc_fb(W, H, var)
 
@@ -302,7 +303,13 @@ def leg_hq(args):
         bpp = 32 if (var & 0xFF) == pcr.HQ else 16
         out[name] = {"frame_ms": round(ms, 4), "Gpts_s": round(n / ms / 1e6, 2),
                      "GB_s": round(bpp * n / ms / 1e6, 1), "hbm_frac": round(bpp * n / ms / 1e6 / HBM_PEAK_GBS, 4)}
+        if name.startswith("hq"):
+            images[name] = img.clone()
         del fb
+    # pixels where the packed form differs from the two-word sums (more than
+    # 1023 points blended into them)
+    out["hq_packed"]["pixels_differing_from_hq"] = int((images["hq_packed"] != images["hq"]).sum())
+    out["hq_packed"]["plain_same_image"] = bool(torch.equal(images["hq_packed"], images["hq_packed_plain"]))
     return {"metric": METRIC, "value": out["hq"]["Gpts_s"], "unit": "Gpts/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": out["hq"]["frame_ms"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+u64",
@@ -736,6 +743,7 @@ def leg_techniques(args):
         "dedup&early-z": pcr.DEDUP | pcr.F_LDS | pcr.F_REDUCE | pcr.F_EARLYZ,
         "HQ(plain)": pcr.HQ | pcr.F_PLAIN,
         "HQ": pcr.HQ,
+        "HQ(packed)": pcr.HQ | pcr.F_HQ_PACKED,
     }
     poses = {"closeup": synth.terrain_closeup(W, H), "oblique": synth.terrain_oblique(W, H),
              "overview": synth.terrain_overview(W, H), "away": synth.terrain_away(W, H)}
@@ -752,11 +760,12 @@ def leg_techniques(args):
             for tname, var in techniques.items():
                 fam = pcr.HQ if (var & 0xFF) == pcr.HQ else pcr.BASIC
                 fb = fbs[fam]
+                layout = fam | (var & pcr.F_HQ_PACKED)      # clear and resolve follow the sums layout
 
                 def frame():
-                    pcr.fb_clear(fb, W, H, fam)
+                    pcr.fb_clear(fb, W, H, layout)
                     pcr.render(d, m, W, H, var, fb)
-                    pcr.resolve(fb, W, H, fam, out=img)
+                    pcr.resolve(fb, W, H, layout, out=img)
                 row[tname] = round(time_frames(frame, args.steps, args.warmup), 4)
                 if tname == "atomicMin":
                     ref.copy_(img)

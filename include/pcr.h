@@ -95,14 +95,28 @@ enum { PCR_BASIC = 0, PCR_DEDUP = 1, PCR_HQ = 2 };
  *   PCR_F_HQ_DEPTH / PCR_F_HQ_COLOR  (PCR_HQ) run only that pass; neither bit
  *                 = both passes in order.  Running the depth pass over several
  *                 point buffers and then the colour pass over the same buffers
- *                 renders their union. */
+ *                 renders their union.
+ *   PCR_F_HQ_PACKED  (PCR_HQ) the single-atomic form of Sec. 3.5.1: the colour
+ *                 sums of a pixel live in one 64-bit word,
+ *                 r << 46 | g << 28 | b << 10 | count (18-bit colour sums, a
+ *                 10-bit count; each contributing point adds its packed value
+ *                 modulo 2^64, so a full field carries into the next one up).
+ *                 Exact while at most 1023 points blend into one pixel; with
+ *                 more, that pixel's colour is wrong (1024 points wrap the
+ *                 count and the pixel resolves empty).  One global atomic per
+ *                 merged update instead of two.  Pass the flag to
+ *                 pcr_fb_clear, pcr_render, pcr_resolve and pcr_resolve_depth
+ *                 alike (the word of pixel k is the k-th 64-bit word of the
+ *                 sums area; the framebuffer size is unchanged).  Not
+ *                 accepted in batch views. */
 enum {
     PCR_F_EARLYZ = 1 << 8,
     PCR_F_REDUCE = 1 << 9,
     PCR_F_LDS = 1 << 10,
     PCR_F_PLAIN = 1 << 11,
     PCR_F_HQ_DEPTH = 1 << 12,
-    PCR_F_HQ_COLOR = 1 << 13
+    PCR_F_HQ_COLOR = 1 << 13,
+    PCR_F_HQ_PACKED = 1 << 14
 };
 
 /* Vertex orders (Sec. 4, Sec. 5). */
@@ -140,7 +154,8 @@ typedef struct pcr_tune {
  *   PCR_HQ: uint32 depth[W*H] (float bits, cleared to 0xFFFFFFFF), then at the
  *     next 256-byte boundary uint64 sum[2*W*H] with sum[2p] = (R sum << 32) |
  *     G sum and sum[2p+1] = (B sum << 32) | count, each word modulo 2^64
- *     (Sec. 3.5 packs the four 32-bit channels into two 64-bit integers).
+ *     (Sec. 3.5 packs the four 32-bit channels into two 64-bit integers);
+ *     with PCR_F_HQ_PACKED, sum[p] is pixel p's packed word (see the flag).
  * Returns 0 for invalid sizes or variants. */
 size_t pcr_fb_bytes(uint32_t w, uint32_t h, int variant);
 

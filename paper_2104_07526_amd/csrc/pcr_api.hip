@@ -36,7 +36,7 @@ int check_variant(int variant) {
     uint32_t flags = (uint32_t)variant & ~0xFFu;
     if (fam != PCR_BASIC && fam != PCR_DEDUP && fam != PCR_HQ)
         return fail(PCR_EINVAL, "unknown variant %d", fam);
-    uint32_t allowed = fam == PCR_HQ ? (kFlagMask | kHqPassMask) : kFlagMask;
+    uint32_t allowed = fam == PCR_HQ ? (kFlagMask | kHqPassMask | PCR_F_HQ_PACKED) : kFlagMask;
     if ((flags & PCR_F_PLAIN) && (flags & (PCR_F_EARLYZ | PCR_F_REDUCE | PCR_F_LDS)))
         return fail(PCR_EINVAL, "PCR_F_PLAIN excludes the other path flags");
     if (flags & ~allowed) return fail(PCR_EINVAL, "flag bits 0x%x do not apply to variant %d", flags & ~allowed, fam);

@@ -532,8 +532,26 @@ __global__ __launch_bounds__(1024) void k_hq_depth(const u32x4 *__restrict__ pts
 
 // HQ colour pass (Sec. 3.5): a point within 1% of its pixel's closest depth
 // (depth <= fl32(closest * 1.01f)) adds (r << 32 | g) and (b << 32 | 1) to the
-// pixel's two 64-bit sums.
-template <int PPT, bool LDS, class Src>
+// pixel's two 64-bit sums.  PACKED (the single-atomic form of Sec. 3.5.1):
+// it adds r << 46 | g << 28 | b << 10 | 1 to one word per pixel, S[pid],
+// modulo 2^64 (exact while at most 1023 points blend into a pixel).  The
+// table's sums pack into that word linearly: R << 46 + G << 28 + B << 10 + n
+// equals the sum of the packed values of its points, modulo 2^64.
+__device__ __forceinline__ u64 packed_sums(u64 rg, u64 ba) {
+    return ((rg >> 32) << 46) + ((rg & 0xFFFFFFFFull) << 28) + ((ba >> 32) << 10) + (ba & 0xFFFFFFFFull);
+}
+
+template <bool PACKED>
+__device__ __forceinline__ void add_sums(u64 *__restrict__ S, uint32_t pid, u64 rg, u64 ba) {
+    if constexpr (PACKED) {
+        gadd_u64(S + pid, packed_sums(rg, ba));
+    } else {
+        gadd_u64(S + 2 * (u64)pid, rg);
+        gadd_u64(S + 2 * (u64)pid + 1, ba);
+    }
+}
+
+template <int PPT, bool LDS, class Src, bool PACKED = false>
 __device__ __forceinline__ void hq_color_tiles(const u32x4 *__restrict__ pts, Tiles tl, const View &v,
                                                const uint32_t *__restrict__ D, u64 *__restrict__ S,
                                                uint32_t hbits, Src src) {
@@ -575,14 +593,12 @@ __device__ __forceinline__ void hq_color_tiles(const u32x4 *__restrict__ pts, Ti
             wave_group_sums(pid, p[j].w, rg, ba, live);
             if (!live) continue;
             if (!LDS) {
-                gadd_u64(S + 2 * (u64)pid, rg);
-                gadd_u64(S + 2 * (u64)pid + 1, ba);
+                add_sums<PACKED>(S, pid, rg, ba);
                 continue;
             }
             uint32_t h = L.slot(pid, par);
             if (h == kNoSlot) {
-                gadd_u64(S + 2 * (u64)pid, rg);
-                gadd_u64(S + 2 * (u64)pid + 1, ba);
+                add_sums<PACKED>(S, pid, rg, ba);
                 continue;
             }
             __hip_atomic_fetch_add(&L.val[h].rg, rg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -599,19 +615,18 @@ __device__ __forceinline__ void hq_color_tiles(const u32x4 *__restrict__ pts, Ti
             L.tag[h] = kEmptyPid;
             L.val[h].rg = 0;
             L.val[h].ba = 0;
-            gadd_u64(S + 2 * (u64)pid, sm.rg);
-            gadd_u64(S + 2 * (u64)pid + 1, sm.ba);
+            add_sums<PACKED>(S, pid, sm.rg, sm.ba);
         }
         lds_barrier();
         par ^= 1u;
     }
 }
 
-template <int PPT, bool LDS, class Src>
+template <int PPT, bool LDS, class Src, bool PACKED = false>
 __global__ __launch_bounds__(1024) void k_hq_color(const u32x4 *__restrict__ pts, Tiles tl, View v,
                                                    const uint32_t *__restrict__ D,
                                                    u64 *__restrict__ S, uint32_t hbits, Src src) {
-    hq_color_tiles<PPT, LDS, Src>(pts, tl, v, D, S, hbits, src);
+    hq_color_tiles<PPT, LDS, Src, PACKED>(pts, tl, v, D, S, hbits, src);
 }
 
 // Single-view passes driven by a batch plan's table: the view is read on the
@@ -666,11 +681,29 @@ __device__ __forceinline__ uint32_t hq_colour(u32x4 s) {
     return (r & 0xFFu) | (g & 0xFFu) << 8 | (b & 0xFFu) << 16 | 0xFF000000u;
 }
 
-__global__ __launch_bounds__(256) void k_resolve_hq(const u32x4 *__restrict__ S,
+// Integer average of one packed word (Sec. 3.5.1): 18-bit colour fields over
+// the 10-bit count.
+__device__ __forceinline__ uint32_t hq_colour_packed(u64 w) {
+    const uint32_t c = (uint32_t)w & 0x3FFu;
+    if (c == 0) return 0u;
+    const uint32_t r = (uint32_t)(w >> 46) & 0x3FFFFu, g = (uint32_t)(w >> 28) & 0x3FFFFu,
+                   b = (uint32_t)(w >> 10) & 0x3FFFFu;
+    return (r / c & 0xFFu) | (g / c & 0xFFu) << 8 | (b / c & 0xFFu) << 16 | 0xFF000000u;
+}
+
+// Colour of pixel i from the sums area: two words per pixel, or one packed.
+template <bool PACKED>
+__device__ __forceinline__ uint32_t hq_pixel(const u64 *__restrict__ S, uint64_t i) {
+    if constexpr (PACKED) return hq_colour_packed(S[i]);
+    else return hq_colour(((const u32x4 *)S)[i]);
+}
+
+template <bool PACKED>
+__global__ __launch_bounds__(256) void k_resolve_hq(const u64 *__restrict__ S,
                                                     uint32_t *__restrict__ out, uint64_t npix) {
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npix; i += stride)
-        out[i] = hq_colour(S[i]);
+        out[i] = hq_pixel<PACKED>(S, i);
 }
 
 // Depth output (Sec. 3.1, closing paragraph): the stored linear depth w, or
@@ -697,14 +730,15 @@ __global__ __launch_bounds__(256) void k_resolve_basic_depth(const u64 *__restri
     }
 }
 
+template <bool PACKED>
 __global__ __launch_bounds__(256) void k_resolve_hq_depth(const uint32_t *__restrict__ D,
-                                                          const u32x4 *__restrict__ S,
+                                                          const u64 *__restrict__ S,
                                                           uint32_t *__restrict__ out,
                                                           float *__restrict__ depth, uint64_t npix,
                                                           int mode, float a, float b, float empty) {
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npix; i += stride) {
-        if (out) out[i] = hq_colour(S[i]);
+        if (out) out[i] = hq_pixel<PACKED>(S, i);
         const uint32_t db = D[i];
         const float d = depth_value(db, mode, a, b);
         depth[i] = db != 0xFFFFFFFFu ? d : empty;
@@ -832,9 +866,18 @@ struct ColorL {
             size_t sm = lds_bytes(hb, 16);
             if (sm > max_lds())
                 return fail(PCR_EINVAL, "tile of %u points needs %zu bytes of LDS", T, sm);
-            if (int rc = allow_lds((const void *)&k_hq_color<P, true, FlatSrc>, sm)) return rc;
-            hipLaunchKernelGGL((k_hq_color<P, true, FlatSrc>), dim3(grid), dim3(L.sh.wg), sm, L.s, L.pts, tl, L.v, D,
-                               S, hb, FlatSrc{});
+            if (L.flags & PCR_F_HQ_PACKED) {
+                if (int rc = allow_lds((const void *)&k_hq_color<P, true, FlatSrc, true>, sm)) return rc;
+                hipLaunchKernelGGL((k_hq_color<P, true, FlatSrc, true>), dim3(grid), dim3(L.sh.wg), sm, L.s, L.pts,
+                                   tl, L.v, D, S, hb, FlatSrc{});
+            } else {
+                if (int rc = allow_lds((const void *)&k_hq_color<P, true, FlatSrc>, sm)) return rc;
+                hipLaunchKernelGGL((k_hq_color<P, true, FlatSrc>), dim3(grid), dim3(L.sh.wg), sm, L.s, L.pts, tl,
+                                   L.v, D, S, hb, FlatSrc{});
+            }
+        } else if (L.flags & PCR_F_HQ_PACKED) {
+            hipLaunchKernelGGL((k_hq_color<P, false, FlatSrc, true>), dim3(grid), dim3(L.sh.wg), 0, L.s, L.pts, tl,
+                               L.v, D, S, 1u, FlatSrc{});
         } else {
             hipLaunchKernelGGL((k_hq_color<P, false, FlatSrc>), dim3(grid), dim3(L.sh.wg), 0, L.s, L.pts, tl, L.v, D,
                                S, 1u, FlatSrc{});
@@ -912,6 +955,7 @@ struct ChunkLaunch {
     void *fb;
     int fam;
     uint32_t pass;  // HQ passes to run
+    bool packed;    // HQ sums in one packed word per pixel (PCR_F_HQ_PACKED)
     Shape sh;
     uint32_t w, h;
     hipStream_t s;
@@ -952,12 +996,17 @@ struct ChunkL {
         if (C.pass & PCR_F_HQ_COLOR) {
             const size_t sm = lds_bytes(hb, 16);
             if (sm > max_lds()) return fail(PCR_EINVAL, "tile of %u points needs %zu bytes of LDS", T, sm);
-            const void *fn = (const void *)&k_hq_color<P, true, ChunkSrc>;
+            const void *fn = C.packed ? (const void *)&k_hq_color<P, true, ChunkSrc, true>
+                                      : (const void *)&k_hq_color<P, true, ChunkSrc>;
             if (int rc = allow_lds(fn, sm)) return rc;
             const uint32_t *D = (const uint32_t *)C.fb;
             u64 *S = (u64 *)((char *)C.fb + hq_depth_bytes(C.w, C.h));
-            hipLaunchKernelGGL((k_hq_color<P, true, ChunkSrc>), dim3(persistent_grid(fn, wg, sm, C.sh.grid)),
-                               dim3(wg), sm, C.s, nullptr, tl, C.v, D, S, hb, C.src);
+            if (C.packed)
+                hipLaunchKernelGGL((k_hq_color<P, true, ChunkSrc, true>), dim3(persistent_grid(fn, wg, sm, C.sh.grid)),
+                                   dim3(wg), sm, C.s, nullptr, tl, C.v, D, S, hb, C.src);
+            else
+                hipLaunchKernelGGL((k_hq_color<P, true, ChunkSrc>), dim3(persistent_grid(fn, wg, sm, C.sh.grid)),
+                                   dim3(wg), sm, C.s, nullptr, tl, C.v, D, S, hb, C.src);
             PCR_LAUNCHED();
         }
         return PCR_OK;
@@ -1020,7 +1069,8 @@ extern "C" int pcr_fb_clear(void *fb, uint32_t w, uint32_t h, int variant, void 
     if ((variant & 0xFF) == PCR_HQ) {
         size_t db = hq_depth_bytes(w, h);
         rc = launch_fill(fb, db, 0xFFFFFFFFu, s);
-        if (rc == PCR_OK) rc = launch_fill((char *)fb + db, 16 * px, 0u, s);
+        // the packed form uses one sum word per pixel
+        if (rc == PCR_OK) rc = launch_fill((char *)fb + db, ((variant & PCR_F_HQ_PACKED) ? 8 : 16) * px, 0u, s);
         return rc;
     }
     return launch_fill(fb, 8 * px, 0xFFFFFFFFu, s);
@@ -1099,7 +1149,8 @@ extern "C" int pcr_render_chunks(const pcr_chunk *chunks, uint32_t nchunks, cons
     PCR_LAUNCHED();
     uint32_t pass = flags & kHqPassMask;
     if (pass == 0) pass = kHqPassMask;
-    ChunkLaunch C{ChunkSrc{chunks, start, nchunks}, make_view(mvp, w, h), fb, fam, pass, sh, w, h, s};
+    ChunkLaunch C{ChunkSrc{chunks, start, nchunks}, make_view(mvp, w, h), fb, fam, pass,
+                  (flags & PCR_F_HQ_PACKED) != 0, sh, w, h, s};
     return by_ppt<ChunkL>(sh.ppt, C);
 }
 
@@ -1115,8 +1166,11 @@ extern "C" int pcr_resolve(const void *fb, uint32_t w, uint32_t h, int variant, 
     uint32_t grid = (uint32_t)(want > 16384 ? 16384 : want);
     hipStream_t s = (hipStream_t)stream;
     if ((variant & 0xFF) == PCR_HQ) {
-        const u32x4 *S = (const u32x4 *)((const char *)fb + hq_depth_bytes(w, h));
-        hipLaunchKernelGGL(k_resolve_hq, dim3(grid), dim3(256), 0, s, S, rgba_out, px);
+        const u64 *S = (const u64 *)((const char *)fb + hq_depth_bytes(w, h));
+        if (variant & PCR_F_HQ_PACKED)
+            hipLaunchKernelGGL(k_resolve_hq<true>, dim3(grid), dim3(256), 0, s, S, rgba_out, px);
+        else
+            hipLaunchKernelGGL(k_resolve_hq<false>, dim3(grid), dim3(256), 0, s, S, rgba_out, px);
     } else {
         hipLaunchKernelGGL(k_resolve_basic, dim3(grid), dim3(256), 0, s, (const u64 *)fb, rgba_out, px);
     }
@@ -1140,9 +1194,13 @@ extern "C" int pcr_resolve_depth(const void *fb, uint32_t w, uint32_t h, int var
     hipStream_t s = (hipStream_t)stream;
     if ((variant & 0xFF) == PCR_HQ) {
         const uint32_t *D = (const uint32_t *)fb;
-        const u32x4 *S = (const u32x4 *)((const char *)fb + hq_depth_bytes(w, h));
-        hipLaunchKernelGGL(k_resolve_hq_depth, dim3(grid), dim3(256), 0, s, D, S, rgba_out, depth_out, px, mode,
-                           a, b, empty);
+        const u64 *S = (const u64 *)((const char *)fb + hq_depth_bytes(w, h));
+        if (variant & PCR_F_HQ_PACKED)
+            hipLaunchKernelGGL(k_resolve_hq_depth<true>, dim3(grid), dim3(256), 0, s, D, S, rgba_out, depth_out, px,
+                               mode, a, b, empty);
+        else
+            hipLaunchKernelGGL(k_resolve_hq_depth<false>, dim3(grid), dim3(256), 0, s, D, S, rgba_out, depth_out, px,
+                               mode, a, b, empty);
     } else {
         hipLaunchKernelGGL(k_resolve_basic_depth, dim3(grid), dim3(256), 0, s, (const u64 *)fb, rgba_out,
                            depth_out, px, mode, a, b, empty);

@@ -27,6 +27,7 @@ F_LDS = 1 << 10
 F_PLAIN = 1 << 11
 F_HQ_DEPTH = 1 << 12
 F_HQ_COLOR = 1 << 13
+F_HQ_PACKED = 1 << 14
 ORDER_MORTON, ORDER_MORTON_SHUFFLE, ORDER_SHUFFLE = 0, 1, 2
 DEPTH_LINEAR, DEPTH_HYPERBOLIC = 0, 1
 

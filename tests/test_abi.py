@@ -68,6 +68,19 @@ def test_render_rejects_bad_variants(variant, msg):
     assert msg in pcr.lib().pcr_last_error().decode()
 
 
+def test_packed_hq_flag_checks():
+    """PCR_F_HQ_PACKED belongs to PCR_HQ only; chunked frames of the other
+    variants refuse it before touching any pointer."""
+    L = pcr.lib()
+    m = (ctypes.c_float * 16)()
+    assert L.pcr_fb_bytes(64, 32, pcr.HQ | pcr.F_HQ_PACKED) == L.pcr_fb_bytes(64, 32, pcr.HQ)
+    assert L.pcr_fb_bytes(64, 32, pcr.DEDUP | pcr.F_HQ_PACKED) == 0
+    assert L.pcr_render(None, 0, m, 4, 4, pcr.BASIC | pcr.F_HQ_PACKED, None, None) == pcr.EINVAL
+    assert "flag bits" in L.pcr_last_error().decode()
+    assert L.pcr_render_chunks(16, 3, m, 4, 4, pcr.DEDUP | pcr.F_HQ_PACKED, 16, 256, 256, None, None) in (
+        pcr.EUNSUPPORTED, pcr.EINVAL)
+
+
 def test_render_rejects_bad_pointers_and_sizes():
     L = pcr.lib()
     m = (ctypes.c_float * 16)()
