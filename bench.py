@@ -46,10 +46,10 @@ HBM_PEAK_GBS = 8000.0
 # kernel sources they were taken on: `src` is the sha256 of the render sources.
 MEASURED_TRAFFIC = {
     # profiles/render_terrain100M_1080p.md
-    "k_basic": {"src": "5938d338d60223fa0e85b252e20127109baed0043eadf1ec679542ccda1e61fe",
-                "fetch_bytes": 1670933501, "write_bytes": 1069193888},
-    "k_dedup<u64>": {"src": "5938d338d60223fa0e85b252e20127109baed0043eadf1ec679542ccda1e61fe",
-                     "fetch_bytes": 1600076082, "write_bytes": 108992512},
+    "k_basic": {"src": "8e0f99f9c8f5985adb75f1d8fca2d0fd21e073d1f86eb589ca36856e3a494280",
+                "fetch_bytes": 1670394535, "write_bytes": 1069193888},
+    "k_dedup<u64>": {"src": "8e0f99f9c8f5985adb75f1d8fca2d0fd21e073d1f86eb589ca36856e3a494280",
+                     "fetch_bytes": 1600070270, "write_bytes": 108992512},
 }
 
 
