@@ -18,8 +18,13 @@ from . import pcr
 CACHE = os.environ.get("PCR_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "pcr_tune.json"))
 _lock = threading.Lock()
 
-# group 1: each view its own single-view pass inside the plan's graph
-BATCH_CANDIDATES = ([{"ppt": p, "group": g} for p in (4, 8) for g in (1, 4, 8, 16, 32)] +
+# group 1: each view its own single-view pass inside the plan's graph, with
+# points per thread 1-16 and workgroups of 64-1024 threads (tiles of at most
+# 4096 points, whose LDS tables fit); group > 1: the batched pass (at most 256
+# threads per workgroup), views per point pass 4-32.
+BATCH_CANDIDATES = ([{"ppt": p, "group": 1, "wg": w} for p in (1, 2, 4, 8, 16) for w in (64, 256, 1024)
+                     if p * w <= 4096] +
+                    [{"ppt": p, "group": g} for p in (4, 8) for g in (4, 8, 16, 32)] +
                     [{"ppt": 8, "group": g, "wg": 64} for g in (4, 8, 16, 32)])
 RENDER_CANDIDATES = [{"ppt": p, "wg": w, "slots": s} for p in (4, 8, 16) for w in (64, 128, 256, 512)
                      for s in (0, 512, 1024, 2048)]
@@ -81,7 +86,10 @@ def tune_batch(points, views, candidates=None, reps=2, use_cache=True):
     table = []
     for c in candidates or BATCH_CANDIDATES:
         print(f"tune_batch: {c}", file=sys.stderr, flush=True)
-        plan = pcr.BatchPlan(points, len(views), tune=c)
+        try:
+            plan = pcr.BatchPlan(points, len(views), tune=c)
+        except pcr.PcrError:
+            continue                     # shape does not fit (LDS)
         try:
             ms = _time(lambda: plan.launch(views), reps)
         finally:
