@@ -335,9 +335,13 @@ struct ChunkSrc {
     const uint64_t *start;
     uint32_t nchunks;
     // Per workgroup (set up in the kernel): the contiguous tile range
-    // [t_next, t_end) and the chunk holding tile t_next.
+    // [t_next, t_end), the chunk `cur` holding tile t_next, and that chunk's
+    // tile range, base and size, kept in registers until a tile leaves it.
     uint64_t t_next, t_end;
     uint32_t cur;
+    uint64_t cur_first, cur_last;  // tiles [cur_first, cur_last) of chunk cur
+    const u32x4 *cur_pts;
+    uint64_t cur_n;
 
     // Last c with start[c] <= t (start[0] = 0 <= t < start[nchunks]).
     __device__ __forceinline__ uint32_t find(uint64_t t) const {
@@ -348,6 +352,13 @@ struct ChunkSrc {
             else hi = mid;
         }
         return lo;
+    }
+    __device__ __forceinline__ void enter(uint32_t c) {
+        cur = c;
+        cur_first = start[c];
+        cur_last = start[c + 1];
+        cur_pts = (const u32x4 *)chunks[c].pts;
+        cur_n = chunks[c].n;
     }
 
     // Static schedule: workgroup b takes the b-th contiguous range of tiles,
@@ -361,7 +372,7 @@ struct ChunkSrc {
         t_next = lo < tl.ntiles ? lo : tl.ntiles;
         t_end = t_next + per_wg < tl.ntiles ? t_next + per_wg : tl.ntiles;
         tl.nblocks = blockIdx.x + (t_end - t_next) * gridDim.x;  // this workgroup's loop count
-        cur = t_next < t_end ? find(t_next) : 0u;
+        if (t_next < t_end) enter(find(t_next));
     }
     __device__ __forceinline__ bool tile(const Tiles &, uint64_t, uint64_t &t) {
         t = t_next++;
@@ -370,12 +381,10 @@ struct ChunkSrc {
     template <int PPT>
     __device__ __forceinline__ uint32_t load(const u32x4 *__restrict__, uint64_t t, uint32_t wg, uint64_t,
                                              u32x4 (&p)[PPT]) {
-        while (start[cur + 1] <= t) ++cur;  // uniform; skips empty and skipped chunks
-        const u32x4 *base = (const u32x4 *)chunks[cur].pts;
-        const uint64_t cn = chunks[cur].n;
-        const uint64_t first = (t - start[cur]) * wg * PPT;  // < cn: the chunk has a tile t
-        load_tile<PPT>(base, first, wg, cn, p);
-        return cn - first < (uint64_t)wg * PPT ? (uint32_t)(cn - first) : wg * PPT;
+        while (cur_last <= t) enter(cur + 1);  // uniform; passes empty and skipped chunks
+        const uint64_t first = (t - cur_first) * wg * PPT;  // < cur_n: the chunk has a tile t
+        load_tile<PPT>(cur_pts, first, wg, cur_n, p);
+        return cur_n - first < (uint64_t)wg * PPT ? (uint32_t)(cur_n - first) : wg * PPT;
     }
 };
 
