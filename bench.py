@@ -46,10 +46,10 @@ HBM_PEAK_GBS = 8000.0
 # kernel sources they were taken on: `src` is the sha256 of the render sources.
 MEASURED_TRAFFIC = {
     # profiles/render_terrain100M_1080p.md
-    "k_basic": {"src": "8e0f99f9c8f5985adb75f1d8fca2d0fd21e073d1f86eb589ca36856e3a494280",
-                "fetch_bytes": 1670394535, "write_bytes": 1069193888},
-    "k_dedup<u64>": {"src": "8e0f99f9c8f5985adb75f1d8fca2d0fd21e073d1f86eb589ca36856e3a494280",
-                     "fetch_bytes": 1600070270, "write_bytes": 108992512},
+    "k_basic": {"src": "50c2301a3297d419da32128e6e87c94af63c4de08003e43ee1eaf9b94a4cc996",
+                "fetch_bytes": 1670621757, "write_bytes": 1069193888},
+    "k_dedup<u64>": {"src": "50c2301a3297d419da32128e6e87c94af63c4de08003e43ee1eaf9b94a4cc996",
+                     "fetch_bytes": 1600064914, "write_bytes": 108992512},
 }
 
 
