@@ -207,8 +207,9 @@ size_t pcr_chunks_scratch_bytes(uint32_t nchunks);
  *   nchunks    at most 2^24; 0 is a no-op.
  *   scratch    device, at least pcr_chunks_scratch_bytes(nchunks) bytes,
  *              256-byte aligned; overwritten (chunk start offsets).
- *   variant    PCR_BASIC, PCR_DEDUP or PCR_HQ, optionally with one PCR_F_HQ_*
- *              pass bit; the other flag bits give PCR_EUNSUPPORTED.
+ *   variant    PCR_BASIC, PCR_DEDUP or PCR_HQ; PCR_HQ optionally with one
+ *              PCR_F_HQ_DEPTH / PCR_F_HQ_COLOR pass bit and PCR_F_HQ_PACKED;
+ *              the other flag bits give PCR_EUNSUPPORTED.
  *   tune       as pcr_render_ex (may be NULL); grid 0 = as many workgroups as
  *              are resident at once.  Tiles of wg*ppt points never span two
  *              chunks (the last tile of a chunk is partial).
