@@ -135,6 +135,8 @@ def _fb_fits(fb, w, h, variant):
 
 
 def _npoints(points):
+    if hasattr(points, "is_contiguous") and not points.is_contiguous():
+        raise ValueError("points must be contiguous")
     nb = points.numel() * points.element_size()
     if nb % 16:
         raise ValueError("points must be 16-byte records")

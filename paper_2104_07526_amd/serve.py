@@ -127,7 +127,19 @@ class GpuBackend:
         self.points = [pcr._npoints(c) for c in clouds]
 
     def bytes_for(self, req: Request) -> int:
-        return _align(pcr.fb_bytes(req.w, req.h, req.variant))
+        """Framebuffer bytes of a request; raises pcr.PcrError for a request
+        that no batch plan can render (so that it is refused alone instead
+        of failing the batch it would join)."""
+        nb = pcr.fb_bytes(req.w, req.h, req.variant)
+        if nb == 0:
+            raise pcr.PcrError(pcr.EINVAL, pcr.lib().pcr_last_error().decode())
+        if req.variant & pcr.F_HQ_PACKED:
+            raise pcr.PcrError(pcr.EUNSUPPORTED, "served requests use the two-word HQ sums (no F_HQ_PACKED)")
+        if req.w * req.h >= 1 << 27:
+            raise pcr.PcrError(pcr.EINVAL, f"{req.w}x{req.h}: served views hold at most 2^27 - 1 pixels")
+        if np.asarray(req.mvp).size != 16:
+            raise pcr.PcrError(pcr.EINVAL, "mvp must hold 16 floats")
+        return _align(nb)
 
     def new_image(self, req: Request):
         return self.torch.empty(req.w * req.h, dtype=self.torch.int32, device=self.device)
@@ -146,19 +158,27 @@ class GpuBackend:
         plan, stream = self.plans[cloud][pi], self.streams[si]
         for img in images:
             img.record_stream(stream)
-        if len(reqs) < self.min_plan_views:
-            # Too few views to share the point stream: the single-view path
-            # (same images), enqueued without any host synchronisation.
-            for r, off, img in zip(reqs, offsets, images):
-                v = pcr.DEDUP if r.variant == pcr.BASIC else r.variant
-                fb = self.base + off
-                pcr.fb_clear(fb, r.w, r.h, v, stream=stream)
-                pcr.render(self.clouds[cloud], r.mvp, r.w, r.h, v, fb, stream=stream)
-                pcr.resolve(fb, r.w, r.h, v, out=img, stream=stream)
-        else:
-            views = [pcr.make_view(r.mvp, r.w, r.h, r.variant, self.base + off, img)
-                     for r, off, img in zip(reqs, offsets, images)]
-            plan.launch(views, stream=stream)
+        try:
+            if len(reqs) < self.min_plan_views:
+                # Too few views to share the point stream: the single-view
+                # path (same images), enqueued without any host
+                # synchronisation.
+                for r, off, img in zip(reqs, offsets, images):
+                    v = pcr.DEDUP if r.variant == pcr.BASIC else r.variant
+                    fb = self.base + off
+                    pcr.fb_clear(fb, r.w, r.h, v, stream=stream)
+                    pcr.render(self.clouds[cloud], r.mvp, r.w, r.h, v, fb, stream=stream)
+                    pcr.resolve(fb, r.w, r.h, v, out=img, stream=stream)
+            else:
+                views = [pcr.make_view(r.mvp, r.w, r.h, r.variant, self.base + off, img)
+                         for r, off, img in zip(reqs, offsets, images)]
+                plan.launch(views, stream=stream)
+        except Exception:
+            # Work enqueued before the failure may still write into these
+            # framebuffers: let it finish before the caller hands their
+            # memory to other requests.
+            stream.synchronize()
+            raise
         ev = self.torch.cuda.Event()
         ev.record(stream)
         self.stream_busy[si] = ev
@@ -223,12 +243,18 @@ class Server:
             self.next_id += 1
             if req.arrival == 0.0:
                 req.arrival = time.perf_counter()
-            need = self.be.bytes_for(req)
-            if need > self.arena.size or not (0 <= req.cloud < len(self.be.points)):
+            why = ""
+            if not (0 <= req.cloud < len(self.be.points)):
+                why = "unknown cloud"
+            else:
+                try:
+                    if self.be.bytes_for(req) > self.arena.size:
+                        why = "request does not fit the framebuffer budget"
+                except Exception as e:  # a request the backend cannot render
+                    why = f"invalid request: {e}"
+            if why:
                 self.rejected += 1
-                fut.set_result(Result(req.rid, None, req.arrival, 0.0, time.perf_counter(), 0, "rejected",
-                                      "request does not fit the framebuffer budget" if need > self.arena.size
-                                      else "unknown cloud"))
+                fut.set_result(Result(req.rid, None, req.arrival, 0.0, time.perf_counter(), 0, "rejected", why))
                 return fut
             self.incoming.append((req, fut))
         return fut

@@ -192,3 +192,10 @@ def test_binding_checks_tensor_sizes_before_enqueueing():
                     scratch=torch.zeros(1 << 20, dtype=torch.uint8))
     with pytest.raises(ValueError, match="image"):
         pcr.make_view(m, W, H, pcr.BASIC, fb, torch.zeros(W * H - 1, dtype=torch.int32))
+    strided = torch.zeros(4, 100, dtype=torch.int32).t()          # 100 records, column-major
+    expanded = torch.zeros(1, 4, dtype=torch.int32).expand(100, 4)  # 100 records over 16 bytes
+    for bad in (strided, expanded):
+        with pytest.raises(ValueError, match="points must be contiguous"):
+            pcr.render(bad, m, W, H, pcr.BASIC, fb)
+        with pytest.raises(ValueError, match="points must be contiguous"):
+            pcr.reorder(bad, pcr.ORDER_MORTON, want_perm=False, scratch=torch.zeros(1 << 20, dtype=torch.uint8))

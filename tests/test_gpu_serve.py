@@ -72,3 +72,31 @@ def test_results_equal_solo_under_load(orc, clouds, streams, max_points, big, be
         assert np.array_equal(out.image.cpu().numpy().view(np.uint32), eimg), r.rid
     assert srv.arena.used == 0, srv.arena.used
     be.close()
+
+
+def test_requests_no_plan_can_render_are_refused_alone(clouds):
+    """A packed-HQ view, an unknown variant, a view past 2^27 - 1 pixels and a
+    short matrix are refused at submit; the valid requests submitted around
+    them are batched together and equal their solo renders."""
+    import torch
+    _, dev = clouds
+    be = GpuBackend(dev, budget_bytes=8 << 20, capacity=6)
+    srv = Server(be, budget_bytes=8 << 20)
+    good = [r for r in mixed_requests(12, seed=31) if r.cloud == 0][:3]
+    assert len(good) == 3
+    m = good[0].mvp
+    bad = [Request(0, m, 64, 48, pcr.HQ | pcr.F_HQ_PACKED), Request(0, m, 64, 48, 7),
+           Request(0, m, 16384, 8192, pcr.BASIC), Request(0, m[:12], 64, 48, pcr.BASIC)]
+    futs = [srv.submit(r) for r in (good[0], bad[0], good[1], bad[1], bad[2], good[2], bad[3])]
+    for i in (1, 3, 4, 6):
+        assert futs[i].done() and futs[i].result().status == "rejected", i
+    srv.drain()
+    torch.cuda.synchronize()
+    for f, r in zip((futs[0], futs[2], futs[5]), good):
+        out = f.result()
+        assert out.status == "ok", (out.status, out.error)
+        assert out.batch_size == 3
+        _, alone = render_frame(dev[r.cloud], r.mvp, r.w, r.h, r.variant)
+        assert np.array_equal(out.image.cpu().numpy().view(np.uint32), alone)
+    assert srv.rejected == 4 and srv.arena.used == 0
+    be.close()

@@ -158,6 +158,27 @@ def test_oversized_request_is_rejected(orc, clouds):
     assert not srv.step()
 
 
+def test_request_the_backend_cannot_render_is_rejected_alone(orc, clouds):
+    """bytes_for raising refuses that request at submit; the requests around
+    it are batched and served."""
+    class Picky(OracleBackend):
+        def bytes_for(self, req):
+            if req.variant == pcr.HQ:
+                raise ValueError("no HQ here")
+            return super().bytes_for(req)
+
+    be = Picky(orc, clouds, capacity=4)
+    srv = Server(be, budget_bytes=1 << 24)
+    reqs = [Request(0, synth.terrain_oblique(32, 18), 32, 18, v) for v in (pcr.BASIC, pcr.HQ, pcr.BASIC)]
+    futs = [srv.submit(r) for r in reqs]
+    assert futs[1].done() and futs[1].result().status == "rejected"
+    assert "no HQ here" in futs[1].result().error
+    srv.drain()
+    assert [futs[0].result().status, futs[2].result().status] == ["ok", "ok"]
+    assert futs[0].result().batch_size == 2
+    assert srv.rejected == 1 and srv.arena.used == 0
+
+
 def test_launch_failure_fails_its_batch_and_server_continues(orc, clouds):
     be = OracleBackend(orc, clouds, capacity=1, fail_variant=pcr.HQ)
     srv = Server(be, budget_bytes=1 << 24)
