@@ -299,6 +299,8 @@ int pcr_batch_create(pcr_batch **plan, const pcr_point *pts, uint64_t n, uint32_
  * nviews <= capacity. */
 int pcr_batch_launch(pcr_batch *plan, const pcr_view *views, uint32_t nviews, void *stream);
 
+/* Waits for the plan's enqueued launches to complete, then frees it (NULL is
+ * a no-op).  Returns PCR_OK. */
 int pcr_batch_destroy(pcr_batch *plan);
 
 /* One-call form of a batch (the views of one launch, as pcr_batch_launch):

@@ -484,14 +484,15 @@ int record(pcr_batch *b, hipStream_t s) {
 
 void destroy(pcr_batch *b) {
     if (!b) return;
+    // Every launch of the plan ends with a record of one of its events: once
+    // they have all completed, no replay of the graph reads its table.
+    for (int i = 0; i < pcr_batch::kRing; ++i)
+        if (b->done[i]) (void)hipEventSynchronize(b->done[i]);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     for (int i = 0; i < pcr_batch::kRing; ++i) {
-        if (b->done[i]) {
-            (void)hipEventSynchronize(b->done[i]);
-            (void)hipEventDestroy(b->done[i]);
-        }
+        if (b->done[i]) (void)hipEventDestroy(b->done[i]);
         if (b->staging[i]) (void)hipHostFree(b->staging[i]);
     }
     if (b->dtable) (void)hipFree(b->dtable);

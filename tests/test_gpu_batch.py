@@ -197,3 +197,46 @@ def test_one_call_batches_over_cached_plans(orc, scene):
             _, eimg = oracle_frame(orc, pts, m, W, H, var)
             assert np.array_equal(img.cpu().numpy().view(np.uint32), eimg), (k, var)
     pcr.release_batch_plans()
+
+
+def test_destroy_and_eviction_wait_for_launches_in_flight(orc, scene):
+    """A plan closed right after its launch, and cached plans evicted (ten
+    launch shapes through a cache of eight) while their launches may still
+    run: every image equals the single-view render, three of them the
+    oracle."""
+    import torch
+    pts, d = scene
+    torch.cuda.synchronize()
+    runs = []
+    plan = pcr.BatchPlan(d, capacity=4)
+    views = make_views(3, seed=700)
+    bufs, pv = [], []
+    for m, W, H, var in views:
+        fb = pcr.alloc_fb(W, H, var)
+        img = torch.zeros(W * H, dtype=torch.int32, device="cuda")
+        bufs.append((fb, img))
+        pv.append(pcr.make_view(m, W, H, var, fb, img))
+    plan.launch(pv)
+    plan.close()
+    runs.append((views, bufs))
+    from paper_2104_07526_amd.tune import BATCH_CANDIDATES
+    tunes = BATCH_CANDIDATES[::2][:10]             # per-view and batched shapes
+    for k, t in enumerate(tunes):
+        views = make_views(3, seed=710 + k)
+        bufs, pv = [], []
+        for m, W, H, var in views:
+            fb = pcr.alloc_fb(W, H, var)
+            img = torch.zeros(W * H, dtype=torch.int32, device="cuda")
+            bufs.append((fb, img))
+            pv.append(pcr.make_view(m, W, H, var, fb, img))
+        pcr.render_batch(d, pv, tune=t)
+        runs.append((views, bufs))
+    torch.cuda.synchronize()
+    for k, (views, bufs) in enumerate(runs):
+        for (m, W, H, var), (fb, img) in zip(views, bufs):
+            _, alone = render_frame(d, m, W, H, var)
+            assert np.array_equal(img.cpu().numpy().view(np.uint32), alone), (k, var)
+    for (m, W, H, var), (_, img) in zip(*runs[0]):
+        _, eimg = oracle_frame(orc, pts, m, W, H, var)
+        assert np.array_equal(img.cpu().numpy().view(np.uint32), eimg)
+    pcr.release_batch_plans()
