@@ -266,7 +266,9 @@ size_t pcr_reorder_scratch_bytes(uint64_t n, int order, uint32_t batch);
  * Morton codes interleave 21-bit cell indices of the cubic bounding box
  * (x in bit 3i, y in 3i+1, z in 3i+2); cell = min(trunc(((v - lo) / size) *
  * 2^21), 2^21 - 1) in float32.  Equal codes keep their input order.  n must be
- * below 2^32; coordinates must be finite. */
+ * below 2^32.  The Morton orders are defined for finite coordinates; with NaN
+ * or infinite ones the order is unspecified, but out is still a permutation
+ * of in (out[j] = in[perm_out[j]]). */
 int pcr_reorder(const pcr_point *in, pcr_point *out, uint32_t *perm_out, uint64_t n, int order,
                 uint32_t batch, uint64_t seed, void *scratch, size_t scratch_bytes, void *stream);
 

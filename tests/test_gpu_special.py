@@ -143,3 +143,22 @@ def test_hostile_floats_batched(orc, cloud, tune):
         assert_same_fb(read_fb(fb, W, H, variant), efb, variant)
         assert np.array_equal(img.cpu().numpy().view(np.uint32), eimg), (name, W, H, variant)
     plan.close()
+
+
+@pytest.mark.parametrize("order", [pcr.ORDER_MORTON, pcr.ORDER_MORTON_SHUFFLE, pcr.ORDER_SHUFFLE])
+def test_reorder_of_non_finite_coordinates_is_a_permutation(orc, cloud, order):
+    """Coordinates outside the reorder's domain (NaN, infinities) leave the
+    Morton order unspecified, but the output is still a permutation of the
+    input with out = in[perm]; the shuffled order, which ignores positions,
+    still equals the oracle's."""
+    import torch
+    from gpu_util import download_points
+    pts, d = cloud
+    out, perm = pcr.reorder(d, order, 128, 9)
+    torch.cuda.synchronize()
+    p = perm.cpu().numpy().astype(np.int64)
+    assert np.array_equal(np.sort(p), np.arange(len(pts)))
+    assert np.array_equal(download_points(out).view(np.uint32).reshape(-1, 4),
+                          pts[p].view(np.uint32).reshape(-1, 4))
+    if order == pcr.ORDER_SHUFFLE:
+        assert np.array_equal(p, orc.reorder(pts, order, 128, 9))
