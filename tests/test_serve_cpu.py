@@ -292,3 +292,21 @@ def test_small_batches_beside_a_big_one_are_capped(orc, clouds):
     assert most_small_with_big == 1 and most_small > 1
     for r, f in zip(reqs, futs):
         assert np.array_equal(f.result().image, solo(orc, clouds[r.cloud], r))
+
+
+def test_gpu_backend_refuses_what_no_batch_plan_renders():
+    """GpuBackend.bytes_for (host only): the aligned framebuffer size of a
+    valid request; PcrError for an unknown variant, the packed HQ flag, views
+    of 2^27 or more pixels and a matrix without 16 floats."""
+    from paper_2104_07526_amd.serve import GpuBackend
+    be = GpuBackend.__new__(GpuBackend)          # no device state is needed for sizes
+    m = synth.terrain_oblique(64, 48)
+    assert be.bytes_for(Request(0, m, 64, 48, pcr.BASIC)) == 8 * 64 * 48
+    assert be.bytes_for(Request(0, m, 100, 30, pcr.HQ)) % 256 == 0
+    bad = [(Request(0, m, 64, 48, 7), pcr.EINVAL), (Request(0, m, 0, 48, pcr.BASIC), pcr.EINVAL),
+           (Request(0, m, 64, 48, pcr.HQ | pcr.F_HQ_PACKED), pcr.EUNSUPPORTED),
+           (Request(0, m, 16384, 8192, pcr.BASIC), pcr.EINVAL), (Request(0, m[:12], 64, 48, pcr.BASIC), pcr.EINVAL)]
+    for req, code in bad:
+        with pytest.raises(pcr.PcrError) as e:
+            be.bytes_for(req)
+        assert e.value.code == code, req
