@@ -702,6 +702,22 @@ def leg_lod(args):
         ms = time_frames(single, args.steps, args.warmup)
         res["single_buffer"] = {"frame_ms": round(ms, 4), "fps": round(1e3 / ms, 1),
                                 "identical": bool(torch.equal(img, ref))}
+        # The same points as one buffer in the table's draw order: separates
+        # the cost of the chunk table from that of the shuffled chunk order.
+        # Gathered on the host (a device index_select of this size returned
+        # a wrong gather on this stack; the leg checks the image below).
+        idx = np.concatenate([np.arange(offs[c], offs[c] + sizes[c]) for c in order])
+        dt = torch.from_numpy(d.cpu().numpy()[idx]).to(d.device)
+        del idx
+
+        def single_table_order():
+            pcr.fb_clear(fb, W, H, var)
+            pcr.render(dt, m, W, H, var, fb)
+            pcr.resolve(fb, W, H, var, out=img)
+        ms = time_frames(single_table_order, args.steps, args.warmup)
+        res["single_buffer_table_order"] = {"frame_ms": round(ms, 4), "fps": round(1e3 / ms, 1),
+                                            "identical": bool(torch.equal(img, ref))}
+        del dt
         out[name] = res
         log(f"lod {name}: {res}")
         del d, tab, fb
