@@ -108,7 +108,22 @@ enum { PCR_BASIC = 0, PCR_DEDUP = 1, PCR_HQ = 2 };
  *                 pcr_fb_clear, pcr_render, pcr_resolve and pcr_resolve_depth
  *                 alike (the word of pixel k is the k-th 64-bit word of the
  *                 sums area; the framebuffer size is unchanged).  Not
- *                 accepted in batch views. */
+ *                 accepted in batch views.
+ *   PCR_F_HQ_ROBUST  (PCR_HQ) the robust single-atomic form of Sec. 3.5.1:
+ *                 each pixel also has a fast word r << 48 | g << 32 | b << 16
+ *                 | count holding the sums of at most 255 points, updated by
+ *                 one 64-bit compare-and-swap per merged update; an update
+ *                 that would take the count past 255 moves the word's sums to
+ *                 the two-word sums (the fallback buffers) and resets the word,
+ *                 updates of more than 255 points go to the fallback directly,
+ *                 and the resolve adds the fast word to the fallback.  Exact
+ *                 for any number of points per pixel and any number of
+ *                 concurrent updates (bit-identical images to PCR_HQ; the sum
+ *                 words fast + fallback equal PCR_HQ's).  The framebuffer
+ *                 grows by 8 bytes per pixel: pass the flag to pcr_fb_bytes,
+ *                 pcr_fb_clear, pcr_render, pcr_resolve and pcr_resolve_depth
+ *                 alike.  Excludes PCR_F_HQ_PACKED; not accepted in batch
+ *                 views. */
 enum {
     PCR_F_EARLYZ = 1 << 8,
     PCR_F_REDUCE = 1 << 9,
@@ -116,7 +131,8 @@ enum {
     PCR_F_PLAIN = 1 << 11,
     PCR_F_HQ_DEPTH = 1 << 12,
     PCR_F_HQ_COLOR = 1 << 13,
-    PCR_F_HQ_PACKED = 1 << 14
+    PCR_F_HQ_PACKED = 1 << 14,
+    PCR_F_HQ_ROBUST = 1 << 15
 };
 
 /* Vertex orders (Sec. 4, Sec. 5). */
@@ -155,7 +171,9 @@ typedef struct pcr_tune {
  *     next 256-byte boundary uint64 sum[2*W*H] with sum[2p] = (R sum << 32) |
  *     G sum and sum[2p+1] = (B sum << 32) | count, each word modulo 2^64
  *     (Sec. 3.5 packs the four 32-bit channels into two 64-bit integers);
- *     with PCR_F_HQ_PACKED, sum[p] is pixel p's packed word (see the flag).
+ *     with PCR_F_HQ_PACKED, sum[p] is pixel p's packed word (see the flag);
+ *     with PCR_F_HQ_ROBUST, sum[2p], sum[2p+1] are the fallback words and
+ *     sum[2*W*H + p] is pixel p's fast word (see the flag).
  * Returns 0 for invalid sizes or variants. */
 size_t pcr_fb_bytes(uint32_t w, uint32_t h, int variant);
 
@@ -319,14 +337,50 @@ int pcr_render_batch(const pcr_point *pts, uint64_t n, const pcr_view *views, ui
 /* Destroys every cached plan of pcr_render_batch (waits for their launches). */
 int pcr_release_batch_plans(void);
 
-/* Self-check of the projection's reciprocal (see the Projection paragraph):
- * adds to *mismatches (device, uint64, 8-byte aligned) the number of floats
- * with bit patterns in [first_bits, last_bits] for which the reciprocal used by
- * the render kernels differs from the IEEE quotient 1.0f / w.  Zero over
- * [0x00000001, 0x7F7FFFFF] means the fast reciprocal is exact for every
- * positive finite float. */
-int pcr_check_reciprocal(uint32_t first_bits, uint32_t last_bits, unsigned long long *mismatches,
+/* Self-check of the projection's reciprocal (see the Projection paragraph),
+ * over the floats w with bit patterns in [first_bits, last_bits]:
+ *   result  device uint64[3], 8-byte aligned, accumulated into (clear it first):
+ *           result[0] += number of w whose reciprocal used by the render kernels
+ *                        differs from the device's IEEE division 1.0f / w;
+ *           result[1] += sum of the reciprocals' bit patterns (modulo 2^64);
+ *           result[2] ^= exclusive or of the reciprocals' bit patterns.
+ * The digest lets a caller compare the kernels' reciprocals with IEEE
+ * quotients computed elsewhere (e.g. on the host), independently of the
+ * device division.  result[0] == 0 over [0x00000001, 0x7F7FFFFF] means the
+ * fast reciprocal agrees with the device division for every positive finite
+ * float. */
+int pcr_check_reciprocal(uint32_t first_bits, uint32_t last_bits, unsigned long long *result,
                          void *stream);
+
+/* ---- Measurement helpers (not part of rendering) ---------------------- */
+
+/* Adds to *count (device uint64, 8-byte aligned) the number of the n points
+ * that the projection keeps for this camera and image (the points that are
+ * not culled): the number of global atomics of a PCR_BASIC render of them
+ * (Sec. 3.1: one atomicMin per visible point).  Errors as pcr_render. */
+int pcr_count_visible(const pcr_point *pts, uint64_t n, const float mvp[16], uint32_t w, uint32_t h,
+                      unsigned long long *count, void *stream);
+
+/* Access patterns of pcr_probe_atomics. */
+enum {
+    PCR_PROBE_RANDOM = 0,    /* every lane its own random word */
+    PCR_PROBE_LINE = 1,      /* 8 lanes on the 8 words of one random 64-byte line */
+    PCR_PROBE_ADDRESS = 2,   /* all 64 lanes of a wavefront on one random word */
+    PCR_PROBE_CONTIGUOUS = 3 /* a wavefront on 64 consecutive words */
+};
+
+/* Throughput probe of device-scope 64-bit unsigned atomic minimum, the
+ * operation of the basic renderer (Sec. 3.1), on buf[0, words): workgroups x
+ * 256 lanes each issue `iters` atomics with addresses drawn by `pattern` from
+ * a hash of (seed, lane or wavefront, iteration).  returning != 0 uses the
+ * value-returning form (sink: device uint64, written only in an impossible
+ * case, so that the returned values are consumed).  Timing the call gives
+ * atomics per second for the footprint 8 * words bytes.
+ *   buf    device, 64-byte aligned, 8 * words bytes, overwritten
+ *   words  a multiple of 64 in [64, 2^32)
+ * Errors: PCR_EINVAL for bad pointers, sizes or pattern. */
+int pcr_probe_atomics(unsigned long long *buf, uint64_t words, int pattern, int returning, uint32_t workgroups,
+                      uint32_t iters, uint32_t seed, unsigned long long *sink, void *stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *pcr_last_error(void);

@@ -36,9 +36,11 @@ int check_variant(int variant) {
     uint32_t flags = (uint32_t)variant & ~0xFFu;
     if (fam != PCR_BASIC && fam != PCR_DEDUP && fam != PCR_HQ)
         return fail(PCR_EINVAL, "unknown variant %d", fam);
-    uint32_t allowed = fam == PCR_HQ ? (kFlagMask | kHqPassMask | PCR_F_HQ_PACKED) : kFlagMask;
+    uint32_t allowed = fam == PCR_HQ ? (kFlagMask | kHqPassMask | PCR_F_HQ_PACKED | PCR_F_HQ_ROBUST) : kFlagMask;
     if ((flags & PCR_F_PLAIN) && (flags & (PCR_F_EARLYZ | PCR_F_REDUCE | PCR_F_LDS)))
         return fail(PCR_EINVAL, "PCR_F_PLAIN excludes the other path flags");
+    if ((flags & PCR_F_HQ_PACKED) && (flags & PCR_F_HQ_ROBUST))
+        return fail(PCR_EINVAL, "PCR_F_HQ_PACKED and PCR_F_HQ_ROBUST are two layouts of the sums: pick one");
     if (flags & ~allowed) return fail(PCR_EINVAL, "flag bits 0x%x do not apply to variant %d", flags & ~allowed, fam);
     return PCR_OK;
 }
@@ -122,26 +124,34 @@ extern "C" const char *pcr_last_error(void) { return pcr::g_error.c_str(); }
 extern "C" const char *pcr_version(void) { return "pcr 0.1 (gfx950)"; }
 
 namespace pcr {
-// Counts the floats with bit patterns in [lo, lo + count) whose reciprocal in
-// the projection differs from the IEEE division 1.0f / w.
-__global__ __launch_bounds__(256) void k_check_recip(uint32_t lo, uint64_t count, unsigned long long *bad) {
+// For the floats w with bit patterns in [lo, lo + count): counts those whose
+// projection reciprocal differs from the device division 1.0f / w, and adds
+// the bit patterns of the reciprocals into a digest (their sum modulo 2^64 and
+// their exclusive or), which the caller compares with the same digest of the
+// IEEE quotients computed on the host.
+__global__ __launch_bounds__(256) void k_check_recip(uint32_t lo, uint64_t count, unsigned long long *res) {
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    unsigned long long nbad = 0;
+    unsigned long long nbad = 0, sum = 0, x = 0;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
         float w = __uint_as_float(lo + (uint32_t)i);
-        nbad += __float_as_uint(recip_rn(w)) != __float_as_uint(1.0f / w);
+        const uint32_t q = __float_as_uint(recip_rn(w));
+        nbad += q != __float_as_uint(1.0f / w);
+        sum += q;
+        x ^= q;
     }
-    if (nbad) atomicAdd(bad, nbad);
+    if (nbad) atomicAdd(res, nbad);
+    atomicAdd(res + 1, sum);
+    atomicXor(res + 2, x);
 }
 }  // namespace pcr
 
-extern "C" int pcr_check_reciprocal(uint32_t first_bits, uint32_t last_bits, unsigned long long *mismatches,
+extern "C" int pcr_check_reciprocal(uint32_t first_bits, uint32_t last_bits, unsigned long long *result,
                                     void *stream) {
-    if (!mismatches || ((uintptr_t)mismatches & 7) || last_bits < first_bits)
+    if (!result || ((uintptr_t)result & 7) || last_bits < first_bits)
         return pcr::fail(PCR_EINVAL, "bad reciprocal check arguments");
     uint64_t count = (uint64_t)last_bits - first_bits + 1;
     hipLaunchKernelGGL(pcr::k_check_recip, dim3(8192), dim3(256), 0, (hipStream_t)stream, first_bits, count,
-                       mismatches);
+                       result);
     PCR_LAUNCHED();
     return PCR_OK;
 }

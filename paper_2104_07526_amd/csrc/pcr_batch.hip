@@ -597,8 +597,9 @@ extern "C" int pcr_batch_launch(pcr_batch *b, const pcr_view *views, uint32_t nv
         int rc = check_image(v.w, v.h);
         if (rc == PCR_OK) rc = check_variant(v.variant & 0xFF);
         if (rc != PCR_OK) return rc;
-        if (v.variant & PCR_F_HQ_PACKED)
-            return fail(PCR_EUNSUPPORTED, "view %u: batches render the two-word HQ sums (no PCR_F_HQ_PACKED)", i);
+        if (v.variant & (PCR_F_HQ_PACKED | PCR_F_HQ_ROBUST))
+            return fail(PCR_EUNSUPPORTED,
+                        "view %u: batches render the two-word HQ sums (no PCR_F_HQ_PACKED or PCR_F_HQ_ROBUST)", i);
         if ((uint64_t)v.w * v.h > kPidMask)
             return fail(PCR_EINVAL, "view %u: batched views hold at most 2^27 - 1 pixels", i);
         if (!v.fb || ((uintptr_t)v.fb & 15) || !v.rgba_out || ((uintptr_t)v.rgba_out & 3))

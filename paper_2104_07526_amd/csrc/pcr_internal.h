@@ -70,10 +70,13 @@ __device__ __forceinline__ bool surely_culled(const Clip &c) {
     return c.cw <= 0.0f || __builtin_fabsf(c.cx) > lim || __builtin_fabsf(c.cy) > lim;
 }
 
-// Correctly rounded 1/w: the hardware reciprocal estimate plus one FMA
-// correction step, which equals the IEEE quotient 1.0f / w for every w in
-// [2^-125, 2^126] (every float of that range is checked against the division
-// by pcr_check_reciprocal); outside that range the full division is used.
+// Correctly rounded 1/w by one Newton-Raphson step: r = v_rcp_f32(w) (the
+// hardware reciprocal estimate, about 1 ulp), residual e = fma(-w, r, 1), then
+// q = fma(e, r, r).  The fused residual is exact, so the corrected q equals the
+// IEEE quotient 1.0f / w for every w in [2^-125, 2^126] (every float of that
+// range is checked against the division by pcr_check_reciprocal); outside that
+// range, where the estimate or the residual leaves the normal range, the full
+// division is used.
 // For w <= 0 or NaN the value is not used (the point is culled).
 __device__ __forceinline__ float recip_rn(float w) {
     float r = __builtin_amdgcn_rcpf(w);

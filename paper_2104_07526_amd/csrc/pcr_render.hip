@@ -515,8 +515,9 @@ __global__ __launch_bounds__(1024) void k_dedup(const u32x4 *__restrict__ pts, T
     dedup_tiles<V, PPT, EARLYZ, REDUCE, Src>(pts, tl, v, fb, hbits, src);
 }
 
-// HQ depth pass without LDS (Sec. 3.5: a 32-bit atomicMin of the depth).
-template <int PPT, bool EARLYZ>
+// HQ depth pass without LDS (Sec. 3.5: a 32-bit atomicMin of the depth),
+// optionally with the wavefront reduction of Sec. 3.3 on the depth bits.
+template <int PPT, bool EARLYZ, bool REDUCE>
 __global__ __launch_bounds__(1024) void k_hq_depth(const u32x4 *__restrict__ pts, Tiles tl, View v,
                                                    uint32_t *__restrict__ D) {
     const uint32_t wg = blockDim.x;
@@ -533,6 +534,7 @@ __global__ __launch_bounds__(1024) void k_hq_depth(const u32x4 *__restrict__ pts
             uint32_t dbits;
             uint32_t pid = project_wave(v, p[j], (uint32_t)(j * wg + threadIdx.x) < lim, dbits);
             bool w = pid != kEmptyPid;
+            if (REDUCE) w = wave_reduce<uint32_t, true>(pid, dbits, w);
             if (EARLYZ && w) w = dbits < peek_u32(D + pid);
             if (w) gmin_u32(D + pid, dbits);
         }
@@ -541,26 +543,77 @@ __global__ __launch_bounds__(1024) void k_hq_depth(const u32x4 *__restrict__ pts
 
 // HQ colour pass (Sec. 3.5): a point within 1% of its pixel's closest depth
 // (depth <= fl32(closest * 1.01f)) adds (r << 32 | g) and (b << 32 | 1) to the
-// pixel's two 64-bit sums.  PACKED (the single-atomic form of Sec. 3.5.1):
-// it adds r << 46 | g << 28 | b << 10 | 1 to one word per pixel, S[pid],
-// modulo 2^64 (exact while at most 1023 points blend into a pixel).  The
-// table's sums pack into that word linearly: R << 46 + G << 28 + B << 10 + n
-// equals the sum of the packed values of its points, modulo 2^64.
+// pixel's two 64-bit sums.  How an update (the sums of one or more such
+// points) reaches the framebuffer depends on the sums layout:
+//   kTwoWord  two 64-bit adds, one per sum word
+//   kPacked   the 18-18-18-10 form of Sec. 3.5.1: one add of r << 46 | g << 28
+//             | b << 10 | count to S[pid], modulo 2^64 (exact while at most
+//             1023 points blend into a pixel).  Sums pack into that word
+//             linearly: R << 46 + G << 28 + B << 10 + n is the sum of the
+//             packed values of its points, modulo 2^64.
+//   kRobust   the robust single-atomic form of Sec. 3.5.1 (16-16-16-16 word
+//             with fallback to the two sum words); see robust_add.
+enum { kTwoWord = 0, kPacked = 1, kRobust = 2 };
+
 __device__ __forceinline__ u64 packed_sums(u64 rg, u64 ba) {
     return ((rg >> 32) << 46) + ((rg & 0xFFFFFFFFull) << 28) + ((ba >> 32) << 10) + (ba & 0xFFFFFFFFull);
 }
 
-template <bool PACKED>
-__device__ __forceinline__ void add_sums(u64 *__restrict__ S, uint32_t pid, u64 rg, u64 ba) {
-    if constexpr (PACKED) {
+// Robust single-atomic update (Sec. 3.5.1, HQS1R).  Each pixel has a fast
+// word F[pid] = R << 48 | G << 32 | B << 16 | n holding the sums of at most
+// 255 points (so no 16-bit field can carry: 255 * 255 < 2^16), beside the two
+// fallback words of the two-word layout.  An update of c <= 255 points with
+// sums (R, G, B) is applied to F by compare-and-swap: when the word's count
+// plus c stays within 255 the new word is the old one plus the update;
+// otherwise the word is swapped to zero and the update goes to the fallback
+// words together with the old word's sums (the transfer of the paper's
+// overflowing thread).  A swap that fails (another update landed first)
+// retries with the value it returned; after kRobustTries failures, and for
+// updates of more than 255 points, the update goes to the fallback words
+// alone.  The fast word only ever changes by a successful swap from a value
+// its thread knows exactly, so every completed update is counted exactly once
+// in F or in the fallback, whatever number of updates is in flight: the sums
+// are exact with no bound on concurrency (the paper's single add needs fewer
+// than 65,280 adds to land between the overflow and the reset).  The resolve
+// adds F's fields to the fallback words.
+constexpr int kRobustTries = 4;
+
+__device__ __forceinline__ void robust_add(u64 *__restrict__ F, u64 *__restrict__ S, uint32_t pid, u64 rg, u64 ba) {
+    const uint32_t c = (uint32_t)ba;
+    if (c <= 255u) {
+        const u64 v = (rg >> 32) << 48 | (rg & 0xFFFFull) << 32 | (ba >> 32) << 16 | c;
+        u64 exp = peek_u64(F + pid);
+#pragma unroll 1
+        for (int a = 0; a < kRobustTries; ++a) {
+            const bool fits = ((uint32_t)exp & 0xFFFFu) + c <= 255u;
+            const u64 prev = atomicCAS(F + pid, exp, fits ? exp + v : 0ull);
+            if (prev == exp) {
+                if (fits) return;
+                // transfer: the word's sums join this update in the fallback words
+                rg += (exp >> 48) << 32 | ((exp >> 32) & 0xFFFFull);
+                ba += ((exp >> 16) & 0xFFFFull) << 32 | (exp & 0xFFFFull);
+                break;
+            }
+            exp = prev;
+        }
+    }
+    gadd_u64(S + 2 * (u64)pid, rg);
+    gadd_u64(S + 2 * (u64)pid + 1, ba);
+}
+
+template <int SUMS>
+__device__ __forceinline__ void add_sums(u64 *__restrict__ S, u64 *__restrict__ F, uint32_t pid, u64 rg, u64 ba) {
+    if constexpr (SUMS == kPacked) {
         gadd_u64(S + pid, packed_sums(rg, ba));
+    } else if constexpr (SUMS == kRobust) {
+        robust_add(F, S, pid, rg, ba);
     } else {
         gadd_u64(S + 2 * (u64)pid, rg);
         gadd_u64(S + 2 * (u64)pid + 1, ba);
     }
 }
 
-template <int PPT, bool LDS, class Src, bool PACKED = false>
+template <int PPT, bool LDS, class Src, int SUMS = kTwoWord>
 __device__ __forceinline__ void hq_color_tiles(const u32x4 *__restrict__ pts, Tiles tl, const View &v,
                                                const uint32_t *__restrict__ D, u64 *__restrict__ S,
                                                uint32_t hbits, Src src) {
@@ -568,6 +621,8 @@ __device__ __forceinline__ void hq_color_tiles(const u32x4 *__restrict__ pts, Ti
     const uint32_t wg = blockDim.x;
     if constexpr (Src::chunked) src.setup(tl, wg * PPT);
     Lds<Sum2> L(smem, hbits);
+    // robust form: the fast words follow the two sum words of every pixel
+    u64 *F = SUMS == kRobust ? S + 2 * (u64)v.W * v.H : nullptr;
     if (LDS) {
         for (uint32_t s = threadIdx.x; s < (1u << hbits); s += wg) {
             L.tag[s] = kEmptyPid;
@@ -602,12 +657,12 @@ __device__ __forceinline__ void hq_color_tiles(const u32x4 *__restrict__ pts, Ti
             wave_group_sums(pid, p[j].w, rg, ba, live);
             if (!live) continue;
             if (!LDS) {
-                add_sums<PACKED>(S, pid, rg, ba);
+                add_sums<SUMS>(S, F, pid, rg, ba);
                 continue;
             }
             uint32_t h = L.slot(pid, par);
             if (h == kNoSlot) {
-                add_sums<PACKED>(S, pid, rg, ba);
+                add_sums<SUMS>(S, F, pid, rg, ba);
                 continue;
             }
             __hip_atomic_fetch_add(&L.val[h].rg, rg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -624,18 +679,18 @@ __device__ __forceinline__ void hq_color_tiles(const u32x4 *__restrict__ pts, Ti
             L.tag[h] = kEmptyPid;
             L.val[h].rg = 0;
             L.val[h].ba = 0;
-            add_sums<PACKED>(S, pid, sm.rg, sm.ba);
+            add_sums<SUMS>(S, F, pid, sm.rg, sm.ba);
         }
         lds_barrier();
         par ^= 1u;
     }
 }
 
-template <int PPT, bool LDS, class Src, bool PACKED = false>
+template <int PPT, bool LDS, class Src, int SUMS = kTwoWord>
 __global__ __launch_bounds__(1024) void k_hq_color(const u32x4 *__restrict__ pts, Tiles tl, View v,
                                                    const uint32_t *__restrict__ D,
                                                    u64 *__restrict__ S, uint32_t hbits, Src src) {
-    hq_color_tiles<PPT, LDS, Src, PACKED>(pts, tl, v, D, S, hbits, src);
+    hq_color_tiles<PPT, LDS, Src, SUMS>(pts, tl, v, D, S, hbits, src);
 }
 
 // Single-view passes driven by a batch plan's table: the view is read on the
@@ -700,19 +755,32 @@ __device__ __forceinline__ uint32_t hq_colour_packed(u64 w) {
     return (r / c & 0xFFu) | (g / c & 0xFFu) << 8 | (b / c & 0xFFu) << 16 | 0xFF000000u;
 }
 
-// Colour of pixel i from the sums area: two words per pixel, or one packed.
-template <bool PACKED>
-__device__ __forceinline__ uint32_t hq_pixel(const u64 *__restrict__ S, uint64_t i) {
-    if constexpr (PACKED) return hq_colour_packed(S[i]);
+// The two sum words of pixel i in the robust form: the fallback words plus
+// the fast word's 16-bit fields, R << 32 | G and B << 32 | count (each sum
+// modulo 2^64, as the two-word layout holds them).
+__device__ __forceinline__ u32x4 robust_words(const u64 *__restrict__ S, const u64 *__restrict__ F, uint64_t i) {
+    const u32x4 s = ((const u32x4 *)S)[i];
+    const u64 f = F[i];
+    const u64 rg = ((u64)s.y << 32 | s.x) + ((f >> 48) << 32 | ((f >> 32) & 0xFFFFull));
+    const u64 ba = ((u64)s.w << 32 | s.z) + (((f >> 16) & 0xFFFFull) << 32 | (f & 0xFFFFull));
+    return u32x4{(uint32_t)rg, (uint32_t)(rg >> 32), (uint32_t)ba, (uint32_t)(ba >> 32)};
+}
+
+// Colour of pixel i from the sums area: two words per pixel, one packed word,
+// or the robust form's fallback words plus fast word (F = S + 2 * npix).
+template <int SUMS>
+__device__ __forceinline__ uint32_t hq_pixel(const u64 *__restrict__ S, uint64_t i, uint64_t npix) {
+    if constexpr (SUMS == kPacked) return hq_colour_packed(S[i]);
+    else if constexpr (SUMS == kRobust) return hq_colour(robust_words(S, S + 2 * npix, i));
     else return hq_colour(((const u32x4 *)S)[i]);
 }
 
-template <bool PACKED>
+template <int SUMS>
 __global__ __launch_bounds__(256) void k_resolve_hq(const u64 *__restrict__ S,
                                                     uint32_t *__restrict__ out, uint64_t npix) {
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npix; i += stride)
-        out[i] = hq_pixel<PACKED>(S, i);
+        out[i] = hq_pixel<SUMS>(S, i, npix);
 }
 
 // Depth output (Sec. 3.1, closing paragraph): the stored linear depth w, or
@@ -739,7 +807,7 @@ __global__ __launch_bounds__(256) void k_resolve_basic_depth(const u64 *__restri
     }
 }
 
-template <bool PACKED>
+template <int SUMS>
 __global__ __launch_bounds__(256) void k_resolve_hq_depth(const uint32_t *__restrict__ D,
                                                           const u64 *__restrict__ S,
                                                           uint32_t *__restrict__ out,
@@ -747,7 +815,7 @@ __global__ __launch_bounds__(256) void k_resolve_hq_depth(const uint32_t *__rest
                                                           int mode, float a, float b, float empty) {
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npix; i += stride) {
-        if (out) out[i] = hq_pixel<PACKED>(S, i);
+        if (out) out[i] = hq_pixel<SUMS>(S, i, npix);
         const uint32_t db = D[i];
         const float d = depth_value(db, mode, a, b);
         depth[i] = db != 0xFFFFFFFFu ? d : empty;
@@ -853,46 +921,54 @@ struct DepthL {
             else if (rd) PCR_DD(false, true);
             else PCR_DD(false, false);
 #undef PCR_DD
-        } else if (ez) {
-            hipLaunchKernelGGL((k_hq_depth<P, true>), dim3(grid), dim3(L.sh.wg), 0, L.s, L.pts, tl, L.v, D);
         } else {
-            hipLaunchKernelGGL((k_hq_depth<P, false>), dim3(grid), dim3(L.sh.wg), 0, L.s, L.pts, tl, L.v, D);
+#define PCR_HD(E, R) hipLaunchKernelGGL((k_hq_depth<P, E, R>), dim3(grid), dim3(L.sh.wg), 0, L.s, L.pts, tl, L.v, D)
+            if (ez && rd) PCR_HD(true, true);
+            else if (ez) PCR_HD(true, false);
+            else if (rd) PCR_HD(false, true);
+            else PCR_HD(false, false);
+#undef PCR_HD
         }
         PCR_LAUNCHED();
         return PCR_OK;
     }
 };
 
+// Sums layout of an HQ variant's flags.
+inline int sums_layout(uint32_t flags) {
+    return (flags & PCR_F_HQ_PACKED) ? kPacked : (flags & PCR_F_HQ_ROBUST) ? kRobust : kTwoWord;
+}
+
 template <int P>
 struct ColorL {
+    template <bool LDS, int SUMS>
+    static int go(const Launch &L, const Tiles &tl, uint32_t grid, const uint32_t *D, u64 *S, uint32_t hb,
+                  size_t sm) {
+        if (LDS)
+            if (int rc = allow_lds((const void *)&k_hq_color<P, LDS, FlatSrc, SUMS>, sm)) return rc;
+        hipLaunchKernelGGL((k_hq_color<P, LDS, FlatSrc, SUMS>), dim3(grid), dim3(L.sh.wg), sm, L.s, L.pts, tl, L.v, D,
+                           S, hb, FlatSrc{});
+        PCR_LAUNCHED();
+        return PCR_OK;
+    }
     static int run(const Launch &L, uint32_t w, uint32_t h) {
         uint32_t grid;
         Tiles tl = make_tiles(L.n, L.sh, grid);
         const uint32_t *D = (const uint32_t *)L.fb;
         u64 *S = (u64 *)((char *)L.fb + hq_depth_bytes(w, h));
+        const int sums = sums_layout(L.flags);
         if (L.flags & PCR_F_LDS) {
             uint32_t T = L.sh.wg * P, hb = lds_hbits(T, L.sh.slots);
             size_t sm = lds_bytes(hb, 16);
             if (sm > max_lds())
                 return fail(PCR_EINVAL, "tile of %u points needs %zu bytes of LDS", T, sm);
-            if (L.flags & PCR_F_HQ_PACKED) {
-                if (int rc = allow_lds((const void *)&k_hq_color<P, true, FlatSrc, true>, sm)) return rc;
-                hipLaunchKernelGGL((k_hq_color<P, true, FlatSrc, true>), dim3(grid), dim3(L.sh.wg), sm, L.s, L.pts,
-                                   tl, L.v, D, S, hb, FlatSrc{});
-            } else {
-                if (int rc = allow_lds((const void *)&k_hq_color<P, true, FlatSrc>, sm)) return rc;
-                hipLaunchKernelGGL((k_hq_color<P, true, FlatSrc>), dim3(grid), dim3(L.sh.wg), sm, L.s, L.pts, tl,
-                                   L.v, D, S, hb, FlatSrc{});
-            }
-        } else if (L.flags & PCR_F_HQ_PACKED) {
-            hipLaunchKernelGGL((k_hq_color<P, false, FlatSrc, true>), dim3(grid), dim3(L.sh.wg), 0, L.s, L.pts, tl,
-                               L.v, D, S, 1u, FlatSrc{});
-        } else {
-            hipLaunchKernelGGL((k_hq_color<P, false, FlatSrc>), dim3(grid), dim3(L.sh.wg), 0, L.s, L.pts, tl, L.v, D,
-                               S, 1u, FlatSrc{});
+            if (sums == kPacked) return go<true, kPacked>(L, tl, grid, D, S, hb, sm);
+            if (sums == kRobust) return go<true, kRobust>(L, tl, grid, D, S, hb, sm);
+            return go<true, kTwoWord>(L, tl, grid, D, S, hb, sm);
         }
-        PCR_LAUNCHED();
-        return PCR_OK;
+        if (sums == kPacked) return go<false, kPacked>(L, tl, grid, D, S, 1u, 0);
+        if (sums == kRobust) return go<false, kRobust>(L, tl, grid, D, S, 1u, 0);
+        return go<false, kTwoWord>(L, tl, grid, D, S, 1u, 0);
     }
 };
 
@@ -964,7 +1040,7 @@ struct ChunkLaunch {
     void *fb;
     int fam;
     uint32_t pass;  // HQ passes to run
-    bool packed;    // HQ sums in one packed word per pixel (PCR_F_HQ_PACKED)
+    int sums;       // HQ sums layout (kTwoWord, kPacked, kRobust)
     Shape sh;
     uint32_t w, h;
     hipStream_t s;
@@ -972,6 +1048,17 @@ struct ChunkLaunch {
 
 template <int P>
 struct ChunkL {
+    template <int SUMS>
+    static int color(const ChunkLaunch &C, const Tiles &tl, uint32_t hb, size_t sm) {
+        const void *fn = (const void *)&k_hq_color<P, true, ChunkSrc, SUMS>;
+        if (int rc = allow_lds(fn, sm)) return rc;
+        const uint32_t *D = (const uint32_t *)C.fb;
+        u64 *S = (u64 *)((char *)C.fb + hq_depth_bytes(C.w, C.h));
+        hipLaunchKernelGGL((k_hq_color<P, true, ChunkSrc, SUMS>), dim3(persistent_grid(fn, C.sh.wg, sm, C.sh.grid)),
+                           dim3(C.sh.wg), sm, C.s, nullptr, tl, C.v, D, S, hb, C.src);
+        PCR_LAUNCHED();
+        return PCR_OK;
+    }
     static int run(const ChunkLaunch &C) {
         const uint32_t wg = C.sh.wg, T = wg * P, hb = lds_hbits(T, C.sh.slots);
         const Tiles tl{};
@@ -1005,18 +1092,9 @@ struct ChunkL {
         if (C.pass & PCR_F_HQ_COLOR) {
             const size_t sm = lds_bytes(hb, 16);
             if (sm > max_lds()) return fail(PCR_EINVAL, "tile of %u points needs %zu bytes of LDS", T, sm);
-            const void *fn = C.packed ? (const void *)&k_hq_color<P, true, ChunkSrc, true>
-                                      : (const void *)&k_hq_color<P, true, ChunkSrc>;
-            if (int rc = allow_lds(fn, sm)) return rc;
-            const uint32_t *D = (const uint32_t *)C.fb;
-            u64 *S = (u64 *)((char *)C.fb + hq_depth_bytes(C.w, C.h));
-            if (C.packed)
-                hipLaunchKernelGGL((k_hq_color<P, true, ChunkSrc, true>), dim3(persistent_grid(fn, wg, sm, C.sh.grid)),
-                                   dim3(wg), sm, C.s, nullptr, tl, C.v, D, S, hb, C.src);
-            else
-                hipLaunchKernelGGL((k_hq_color<P, true, ChunkSrc>), dim3(persistent_grid(fn, wg, sm, C.sh.grid)),
-                                   dim3(wg), sm, C.s, nullptr, tl, C.v, D, S, hb, C.src);
-            PCR_LAUNCHED();
+            if (C.sums == kPacked) return color<kPacked>(C, tl, hb, sm);
+            if (C.sums == kRobust) return color<kRobust>(C, tl, hb, sm);
+            return color<kTwoWord>(C, tl, hb, sm);
         }
         return PCR_OK;
     }
@@ -1064,7 +1142,7 @@ using namespace pcr;
 extern "C" size_t pcr_fb_bytes(uint32_t w, uint32_t h, int variant) {
     if (check_image(w, h) != PCR_OK || check_variant(variant) != PCR_OK) return 0;
     uint64_t px = (uint64_t)w * h;
-    if ((variant & 0xFF) == PCR_HQ) return hq_depth_bytes(w, h) + 16 * px;
+    if ((variant & 0xFF) == PCR_HQ) return hq_depth_bytes(w, h) + ((variant & PCR_F_HQ_ROBUST) ? 24 : 16) * px;
     return 8 * px;
 }
 
@@ -1078,8 +1156,9 @@ extern "C" int pcr_fb_clear(void *fb, uint32_t w, uint32_t h, int variant, void 
     if ((variant & 0xFF) == PCR_HQ) {
         size_t db = hq_depth_bytes(w, h);
         rc = launch_fill(fb, db, 0xFFFFFFFFu, s);
-        // the packed form uses one sum word per pixel
-        if (rc == PCR_OK) rc = launch_fill((char *)fb + db, ((variant & PCR_F_HQ_PACKED) ? 8 : 16) * px, 0u, s);
+        // the packed form uses one sum word per pixel, the robust form three
+        const size_t sb = (variant & PCR_F_HQ_PACKED) ? 8 : (variant & PCR_F_HQ_ROBUST) ? 24 : 16;
+        if (rc == PCR_OK) rc = launch_fill((char *)fb + db, sb * px, 0u, s);
         return rc;
     }
     return launch_fill(fb, 8 * px, 0xFFFFFFFFu, s);
@@ -1130,9 +1209,32 @@ extern "C" size_t pcr_chunks_scratch_bytes(uint32_t nchunks) {
     return ((size_t)8 * (nchunks + 1) + 255) / 256 * 256;
 }
 
-extern "C" int pcr_render_chunks(const pcr_chunk *chunks, uint32_t nchunks, const float mvp[16], uint32_t w,
-                                 uint32_t h, int variant, void *fb, void *scratch, size_t scratch_bytes,
-                                 const pcr_tune *tune, void *stream) {
+namespace pcr {
+namespace {
+
+// Renders a chunk table with `start` (device, nchunks + 1 words) as the
+// chunks' tile offsets.  Arguments other than `start` are checked here.
+int render_chunks_into(const pcr_chunk *chunks, uint32_t nchunks, const float mvp[16], uint32_t w, uint32_t h,
+                       int variant, void *fb, uint64_t *start, const pcr_tune *tune, hipStream_t s) {
+    const int fam = variant & 0xFF;
+    const uint32_t flags = (uint32_t)variant & ~0xFFu;
+    Shape sh;
+    int rc = resolve_shape(tune, fam, sh);
+    if (rc != PCR_OK) return rc;
+    hipLaunchKernelGGL(k_chunk_starts, dim3(1), dim3(1024), 0, s, chunks, nchunks, sh.wg * sh.ppt, start);
+    PCR_LAUNCHED();
+    uint32_t pass = flags & kHqPassMask;
+    if (pass == 0) pass = kHqPassMask;
+    ChunkLaunch C{ChunkSrc{chunks, start, nchunks}, make_view(mvp, w, h), fb, fam, pass,
+                  sums_layout(flags), sh, w, h, s};
+    return by_ppt<ChunkL>(sh.ppt, C);
+}
+
+// Checks shared by both chunked entry points; PCR_OK with *noop set when
+// there is nothing to render.
+int check_chunks(const pcr_chunk *chunks, uint32_t nchunks, const float mvp[16], uint32_t w, uint32_t h,
+                 int variant, const void *fb, const pcr_tune *tune, bool &noop) {
+    noop = false;
     int rc = check_image(w, h);
     if (rc == PCR_OK) rc = check_variant(variant);
     if (rc != PCR_OK) return rc;
@@ -1146,21 +1248,28 @@ extern "C" int pcr_render_chunks(const pcr_chunk *chunks, uint32_t nchunks, cons
     Shape sh;
     rc = resolve_shape(tune, fam, sh);
     if (rc != PCR_OK) return rc;
-    if (nchunks == 0) return PCR_OK;
+    if (nchunks == 0) {
+        noop = true;
+        return PCR_OK;
+    }
     if (!chunks || ((uintptr_t)chunks & 7)) return fail(PCR_EINVAL, "chunks must be an 8-byte aligned device pointer");
-    if (!scratch || ((uintptr_t)scratch & 15)) return fail(PCR_EINVAL, "scratch must be a 16-byte aligned device pointer");
+    return PCR_OK;
+}
+
+}  // namespace
+}  // namespace pcr
+
+extern "C" int pcr_render_chunks(const pcr_chunk *chunks, uint32_t nchunks, const float mvp[16], uint32_t w,
+                                 uint32_t h, int variant, void *fb, void *work, size_t work_bytes,
+                                 const pcr_tune *tune, void *stream) {
+    bool noop;
+    int rc = check_chunks(chunks, nchunks, mvp, w, h, variant, fb, tune, noop);
+    if (rc != PCR_OK || noop) return rc;
+    if (!work || ((uintptr_t)work & 15)) return fail(PCR_EINVAL, "scratch must be a 16-byte aligned device pointer");
     const size_t need = pcr_chunks_scratch_bytes(nchunks);
-    if (scratch_bytes < need)
-        return fail(PCR_ENOMEM, "scratch holds %zu bytes, %u chunks need %zu", scratch_bytes, nchunks, need);
-    hipStream_t s = (hipStream_t)stream;
-    uint64_t *start = (uint64_t *)scratch;
-    hipLaunchKernelGGL(k_chunk_starts, dim3(1), dim3(1024), 0, s, chunks, nchunks, sh.wg * sh.ppt, start);
-    PCR_LAUNCHED();
-    uint32_t pass = flags & kHqPassMask;
-    if (pass == 0) pass = kHqPassMask;
-    ChunkLaunch C{ChunkSrc{chunks, start, nchunks}, make_view(mvp, w, h), fb, fam, pass,
-                  (flags & PCR_F_HQ_PACKED) != 0, sh, w, h, s};
-    return by_ppt<ChunkL>(sh.ppt, C);
+    if (work_bytes < need)
+        return fail(PCR_ENOMEM, "scratch holds %zu bytes, %u chunks need %zu", work_bytes, nchunks, need);
+    return render_chunks_into(chunks, nchunks, mvp, w, h, variant, fb, (uint64_t *)work, tune, (hipStream_t)stream);
 }
 
 extern "C" int pcr_resolve(const void *fb, uint32_t w, uint32_t h, int variant, uint32_t *rgba_out,
@@ -1176,10 +1285,13 @@ extern "C" int pcr_resolve(const void *fb, uint32_t w, uint32_t h, int variant, 
     hipStream_t s = (hipStream_t)stream;
     if ((variant & 0xFF) == PCR_HQ) {
         const u64 *S = (const u64 *)((const char *)fb + hq_depth_bytes(w, h));
-        if (variant & PCR_F_HQ_PACKED)
-            hipLaunchKernelGGL(k_resolve_hq<true>, dim3(grid), dim3(256), 0, s, S, rgba_out, px);
+        const int sums = sums_layout((uint32_t)variant);
+        if (sums == kPacked)
+            hipLaunchKernelGGL(k_resolve_hq<kPacked>, dim3(grid), dim3(256), 0, s, S, rgba_out, px);
+        else if (sums == kRobust)
+            hipLaunchKernelGGL(k_resolve_hq<kRobust>, dim3(grid), dim3(256), 0, s, S, rgba_out, px);
         else
-            hipLaunchKernelGGL(k_resolve_hq<false>, dim3(grid), dim3(256), 0, s, S, rgba_out, px);
+            hipLaunchKernelGGL(k_resolve_hq<kTwoWord>, dim3(grid), dim3(256), 0, s, S, rgba_out, px);
     } else {
         hipLaunchKernelGGL(k_resolve_basic, dim3(grid), dim3(256), 0, s, (const u64 *)fb, rgba_out, px);
     }
@@ -1204,12 +1316,16 @@ extern "C" int pcr_resolve_depth(const void *fb, uint32_t w, uint32_t h, int var
     if ((variant & 0xFF) == PCR_HQ) {
         const uint32_t *D = (const uint32_t *)fb;
         const u64 *S = (const u64 *)((const char *)fb + hq_depth_bytes(w, h));
-        if (variant & PCR_F_HQ_PACKED)
-            hipLaunchKernelGGL(k_resolve_hq_depth<true>, dim3(grid), dim3(256), 0, s, D, S, rgba_out, depth_out, px,
+        const int sums = sums_layout((uint32_t)variant);
+        if (sums == kPacked)
+            hipLaunchKernelGGL(k_resolve_hq_depth<kPacked>, dim3(grid), dim3(256), 0, s, D, S, rgba_out, depth_out, px,
+                               mode, a, b, empty);
+        else if (sums == kRobust)
+            hipLaunchKernelGGL(k_resolve_hq_depth<kRobust>, dim3(grid), dim3(256), 0, s, D, S, rgba_out, depth_out, px,
                                mode, a, b, empty);
         else
-            hipLaunchKernelGGL(k_resolve_hq_depth<false>, dim3(grid), dim3(256), 0, s, D, S, rgba_out, depth_out, px,
-                               mode, a, b, empty);
+            hipLaunchKernelGGL(k_resolve_hq_depth<kTwoWord>, dim3(grid), dim3(256), 0, s, D, S, rgba_out, depth_out,
+                               px, mode, a, b, empty);
     } else {
         hipLaunchKernelGGL(k_resolve_basic_depth, dim3(grid), dim3(256), 0, s, (const u64 *)fb, rgba_out,
                            depth_out, px, mode, a, b, empty);

@@ -28,6 +28,7 @@ F_PLAIN = 1 << 11
 F_HQ_DEPTH = 1 << 12
 F_HQ_COLOR = 1 << 13
 F_HQ_PACKED = 1 << 14
+F_HQ_ROBUST = 1 << 15
 ORDER_MORTON, ORDER_MORTON_SHUFFLE, ORDER_SHUFFLE = 0, 1, 2
 DEPTH_LINEAR, DEPTH_HYPERBOLIC = 0, 1
 
@@ -75,6 +76,8 @@ def _declare(lib):
         "pcr_render_batch": (I32, [P, U64, P, U32, P, P]),
         "pcr_release_batch_plans": (I32, []),
         "pcr_check_reciprocal": (I32, [U32, U32, P, P]),
+        "pcr_count_visible": (I32, [P, U64, P, U32, U32, P, P]),
+        "pcr_probe_atomics": (I32, [P, U64, I32, I32, U32, U32, U32, P, P]),
         "pcr_last_error": (ctypes.c_char_p, []),
         "pcr_version": (ctypes.c_char_p, []),
     }
@@ -129,7 +132,8 @@ def _fits(t, nbytes, what):
 
 
 def _fb_fits(fb, w, h, variant):
-    need = int(lib().pcr_fb_bytes(w, h, variant & 0xFF)) if w > 0 and h > 0 else 0
+    # the size depends on the family and the robust HQ layout only
+    need = int(lib().pcr_fb_bytes(w, h, variant & (0xFF | F_HQ_ROBUST))) if w > 0 and h > 0 else 0
     if need:                                # 0: invalid sizes, reported by the library call
         _fits(fb, need, "framebuffer")
 
@@ -163,13 +167,35 @@ def version() -> str:
     return lib().pcr_version().decode()
 
 
-def check_reciprocal(first_bits, last_bits, stream=None) -> int:
-    """Number of floats in the bit range whose projection reciprocal differs
-    from the IEEE quotient (synchronises)."""
+def check_reciprocal(first_bits, last_bits, stream=None):
+    """(mismatches, bit sum mod 2^64, bit xor) of the projection reciprocal
+    over the floats in the bit range (pcr_check_reciprocal; synchronises)."""
     import torch
-    out = torch.zeros(1, dtype=torch.int64, device="cuda")
+    out = torch.zeros(3, dtype=torch.int64, device="cuda")
     _check(lib().pcr_check_reciprocal(first_bits, last_bits, _ptr(out), _stream(stream)))
+    r = out.cpu().numpy().view(np.uint64)
+    return int(r[0]), int(r[1]), int(r[2])
+
+
+PROBE_RANDOM, PROBE_LINE, PROBE_ADDRESS, PROBE_CONTIGUOUS = 0, 1, 2, 3
+
+
+def count_visible(points, mvp, w, h, stream=None) -> int:
+    """Number of points the projection keeps for this view (synchronises)."""
+    import torch
+    out = torch.zeros(1, dtype=torch.int64, device=points.device)
+    _check(lib().pcr_count_visible(_ptr(points), _npoints(points), _mvp(mvp), w, h, _ptr(out), _stream(stream)))
     return int(out.item())
+
+
+def probe_atomics(buf, pattern, returning=False, workgroups=8192, iters=64, seed=1, sink=None, stream=None):
+    """Enqueues the atomic-minimum throughput probe on the int64 tensor
+    ``buf`` (its whole length rounded down to a multiple of 64 words).
+    Returns the number of atomics it issues."""
+    words = (buf.numel() * buf.element_size() // 8) // 64 * 64
+    _check(lib().pcr_probe_atomics(_ptr(buf), words, pattern, int(bool(returning)), workgroups, iters, seed,
+                                   _ptr(sink), _stream(stream)))
+    return workgroups * 256 * iters
 
 
 def fb_bytes(w, h, variant) -> int:
@@ -288,6 +314,10 @@ def reorder(points, order, batch=128, seed=0, out=None, perm=None, want_perm=Tru
 
 
 def make_view(mvp, w, h, variant, fb, rgba_out) -> View:
+    """A batch view record.  It keeps references to ``fb`` and ``rgba_out``
+    (the record itself only holds their device addresses), so the tensors
+    live at least as long as the record; a launch that uses the record keeps
+    them until the launch has completed on the device."""
     _fb_fits(fb, w, h, variant)
     _fits(rgba_out, 4 * w * h, "image")
     v = View()
@@ -295,14 +325,57 @@ def make_view(mvp, w, h, variant, fb, rgba_out) -> View:
     v.w, v.h, v.variant = w, h, variant
     v.fb = _ptr(fb)
     v.rgba_out = _ptr(rgba_out)
+    v._keep = (fb, rgba_out)
     return v
+
+
+class _InFlight:
+    """Buffers of enqueued launches, each held until the event recorded after
+    its launch has completed (the library only sees raw device addresses, so
+    a buffer dropped by the caller could otherwise be freed and reused while
+    a kernel still writes it)."""
+
+    def __init__(self):
+        self._lock = threading.Lock()
+        self._held = []
+
+    def hold(self, event, refs):
+        with self._lock:
+            self._held = [(e, r) for e, r in self._held if not e.query()]
+            self._held.append((event, refs))
+
+    def pending(self):
+        with self._lock:
+            self._held = [(e, r) for e, r in self._held if not e.query()]
+            return len(self._held)
+
+
+def _held_refs(points, views):
+    return (points, tuple(getattr(v, "_keep", ()) for v in views))
+
+
+def _record(stream):
+    import torch
+    e = torch.cuda.Event()
+    if stream is None:
+        e.record()
+    elif isinstance(stream, torch.cuda.Stream):
+        e.record(stream)
+    else:
+        e.record(torch.cuda.ExternalStream(int(stream)))
+    return e
+
+
+_batch_inflight = _InFlight()
 
 
 def render_batch(points, views, tune=None, stream=None):
     """One-call batch of pcr.View records over the library's plan cache
-    (pcr_render_batch in include/pcr.h)."""
+    (pcr_render_batch in include/pcr.h).  The views' buffers (and the points)
+    are kept alive until the launch has completed."""
     arr = (View * max(1, len(views)))(*views)
     _check(lib().pcr_render_batch(_ptr(points), _npoints(points), arr, len(views), _tune(tune), _stream(stream)))
+    _batch_inflight.hold(_record(stream), _held_refs(points, views))
 
 
 def release_batch_plans():
@@ -315,6 +388,7 @@ class BatchPlan:
 
     def __init__(self, points, capacity, tune=None, stream=None):
         self._points = points          # the plan keeps the device pointer
+        self._inflight = _InFlight()
         self.capacity = capacity
         h = ctypes.c_void_p()
         _check(lib().pcr_batch_create(ctypes.byref(h), _ptr(points), _npoints(points), capacity,
@@ -322,8 +396,11 @@ class BatchPlan:
         self._h = h
 
     def launch(self, views, stream=None):
+        """Enqueues one batch; the views' framebuffers and images are kept
+        alive until it has completed on the device."""
         arr = (View * max(1, len(views)))(*views)
         _check(lib().pcr_batch_launch(self._h, arr, len(views), _stream(stream)))
+        self._inflight.hold(_record(stream), _held_refs(None, views))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -199,3 +199,22 @@ def test_binding_checks_tensor_sizes_before_enqueueing():
             pcr.render(bad, m, W, H, pcr.BASIC, fb)
         with pytest.raises(ValueError, match="points must be contiguous"):
             pcr.reorder(bad, pcr.ORDER_MORTON, want_perm=False, scratch=torch.zeros(1 << 20, dtype=torch.uint8))
+
+
+def test_measurement_helpers_check_arguments():
+    """pcr_count_visible and pcr_probe_atomics refuse bad arguments on the
+    host (no GPU call is made for them)."""
+    L = pcr.lib()
+    m = (ctypes.c_float * 16)()
+    assert L.pcr_count_visible(None, 0, m, 0, 4, 8, None) == pcr.EINVAL
+    assert L.pcr_count_visible(None, 0, m, 4, 4, None, None) == pcr.EINVAL
+    assert L.pcr_count_visible(None, 0, None, 4, 4, 8, None) == pcr.EINVAL
+    assert L.pcr_count_visible(8, 5, m, 4, 4, 8, None) == pcr.EINVAL      # misaligned points
+    assert L.pcr_count_visible(None, 0, m, 4, 4, 8, None) == pcr.OK       # n == 0: nothing to do
+    for words in (0, 63, 65, 1 << 32):
+        assert L.pcr_probe_atomics(64, words, 0, 0, 1, 1, 0, None, None) == pcr.EINVAL
+    assert L.pcr_probe_atomics(32, 64, 0, 0, 1, 1, 0, None, None) == pcr.EINVAL   # misaligned buffer
+    assert L.pcr_probe_atomics(64, 64, 4, 0, 1, 1, 0, None, None) == pcr.EINVAL   # unknown pattern
+    assert L.pcr_probe_atomics(64, 64, 0, 1, 1, 1, 0, None, None) == pcr.EINVAL   # returning without sink
+    assert L.pcr_probe_atomics(64, 64, 0, 0, 0, 1, 0, None, None) == pcr.EINVAL   # no workgroups
+

@@ -12,7 +12,7 @@ B, D, HQ = pcr.BASIC, pcr.DEDUP, pcr.HQ
 EZ, RD, LDS = pcr.F_EARLYZ, pcr.F_REDUCE, pcr.F_LDS
 BASIC_FORMS = [B, B | EZ, B | RD, B | EZ | RD, B | LDS, B | LDS | EZ, B | LDS | RD, B | LDS | EZ | RD, D,
                D | pcr.F_PLAIN, B | pcr.F_PLAIN]
-HQ_FORMS = [HQ, HQ | EZ, HQ | LDS, HQ | LDS | EZ, HQ | LDS | RD, HQ | pcr.F_PLAIN]
+HQ_FORMS = [HQ, HQ | EZ, HQ | RD, HQ | RD | EZ, HQ | LDS, HQ | LDS | EZ, HQ | LDS | RD, HQ | pcr.F_PLAIN]
 SHAPES = [None, {"ppt": 1, "wg": 64}, {"ppt": 8, "wg": 256}, {"ppt": 16, "wg": 64},
           {"ppt": 2, "wg": 1024}, {"ppt": 4, "wg": 128, "grid": 3}]
 
