@@ -152,27 +152,38 @@ void oracle_render_hq_depth(const struct opoint *pts, uint64_t n, const float *m
     }
 }
 
-/* Colour pass: a point contributes when its depth is at most the closest depth
- * of its pixel times 1.01; the red and green sums share one 64-bit word
- * (red in the high half), blue and the count the other (blue high). */
+/* Colour pass (Sec. 3.5): a point blends into its pixel when its depth is at
+ * most the pixel's closest depth times 1.01.  Each pixel gathers four exact
+ * sums over its blending points -- red, green, blue and their number -- and
+ * the framebuffer stores them in the paper's two 64-bit words: the red sum in
+ * the upper half of the first word over the green sum, the blue sum in the
+ * upper half of the second over the count.  A call adds this call's sums to
+ * the stored words as the 64-bit integer (sum_hi * 2^32 + sum_lo) modulo 2^64,
+ * which is what adding every point's packed value modulo 2^64 amounts to (a
+ * low sum past 32 bits carries into the high half). */
 void oracle_render_hq_color(const struct opoint *pts, uint64_t n, const float *m,
                             uint32_t W, uint32_t H, const uint32_t *D,
                             uint64_t *RG, uint64_t *BA)
 {
+    uint64_t npix = (uint64_t)W * H;
+    uint64_t *sum = calloc(4 * npix + 1, sizeof(uint64_t)); /* [channel][pixel]: r, g, b, count */
+    if (!sum)
+        abort();
     for (uint64_t i = 0; i < n; ++i) {
         uint32_t pid, dbits;
         if (!oracle_project(m, W, H, pts[i].x, pts[i].y, pts[i].z, &pid, &dbits))
             continue;
-        float depth = u2f(dbits);
-        float limit = u2f(D[pid]) * 1.01f;
-        if (depth <= limit) {
-            uint64_t r = pts[i].rgba & 0xFFu;
-            uint64_t g = (pts[i].rgba >> 8) & 0xFFu;
-            uint64_t b = (pts[i].rgba >> 16) & 0xFFu;
-            RG[pid] += (r << 32) | g;
-            BA[pid] += (b << 32) | 1u;
-        }
+        if (!(u2f(dbits) <= u2f(D[pid]) * 1.01f))
+            continue;
+        for (int c = 0; c < 3; ++c)
+            sum[c * npix + pid] += (pts[i].rgba >> (8 * c)) & 0xFFu;
+        sum[3 * npix + pid] += 1;
     }
+    for (uint64_t p = 0; p < npix; ++p) {
+        RG[p] += (sum[p] << 32) + sum[npix + p];
+        BA[p] += (sum[2 * npix + p] << 32) + sum[3 * npix + p];
+    }
+    free(sum);
 }
 
 /* Both passes over one cloud, in the paper's order: depth, then colour. */
@@ -183,21 +194,24 @@ void oracle_render_hq(const struct opoint *pts, uint64_t n, const float *m,
     oracle_render_hq_color(pts, n, m, W, H, D, RG, BA);
 }
 
-/* Resolve: integer average of each channel sum over the count. */
+/* Resolve (Sec. 3.5): each channel's sum divided by the count, truncating;
+ * the four 32-bit fields are read back from the two words (red = upper half
+ * of the first, green = its lower half, blue = upper half of the second,
+ * count = its lower half); alpha 255; a pixel with count 0 resolves to 0. */
 void oracle_resolve_hq(const uint64_t *RG, const uint64_t *BA, uint32_t W, uint32_t H,
                        uint32_t *out)
 {
     for (uint64_t p = 0; p < (uint64_t)W * H; ++p) {
-        uint64_t a = BA[p] & 0xFFFFFFFFull;
-        if (a == 0) {
+        uint64_t field[4] = {RG[p] >> 32, RG[p] & 0xFFFFFFFFull, BA[p] >> 32, BA[p] & 0xFFFFFFFFull};
+        uint64_t count = field[3];
+        if (count == 0) {
             out[p] = 0;
             continue;
         }
-        uint64_t r = (RG[p] >> 32) / a;
-        uint64_t g = (RG[p] & 0xFFFFFFFFull) / a;
-        uint64_t b = (BA[p] >> 32) / a;
-        out[p] = (uint32_t)(r & 0xFFu) | (uint32_t)(g & 0xFFu) << 8 |
-                 (uint32_t)(b & 0xFFu) << 16 | 0xFF000000u;
+        uint32_t colour = 0xFF000000u;
+        for (int c = 0; c < 3; ++c)
+            colour |= (uint32_t)((field[c] / count) & 0xFFu) << (8 * c);
+        out[p] = colour;
     }
 }
 

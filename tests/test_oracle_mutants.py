@@ -36,12 +36,15 @@ MUTANTS = [
     ("max instead of min", [("if (key < fb[pid])", "if (key > fb[pid] || fb[pid] == 0xFFFFFFFFFFFFFFFFull)")], []),
     ("resolve shows depth", [("(uint32_t)fb[p];", "(uint32_t)(fb[p] >> 32);")], []),
     ("epsilon 10%", [("* 1.01f", "* 1.1f")], []),
-    ("strict threshold", [("if (depth <= limit)", "if (depth < limit)")], []),
-    ("red and green swapped", [("RG[pid] += (r << 32) | g;", "RG[pid] += (g << 32) | r;")], []),
-    ("count of two", [("BA[pid] += (b << 32) | 1u;", "BA[pid] += (b << 32) | 2u;")], []),
-    ("green from the red half", [("uint64_t g = (RG[p] & 0xFFFFFFFFull) / a;",
-                                  "uint64_t g = (RG[p] >> 32) / a;")], []),
-    ("hq alpha 0", [("(uint32_t)(b & 0xFFu) << 16 | 0xFF000000u", "(uint32_t)(b & 0xFFu) << 16")], []),
+    ("strict threshold", [("if (!(u2f(dbits) <= u2f(D[pid]) * 1.01f))", "if (!(u2f(dbits) < u2f(D[pid]) * 1.01f))")],
+     []),
+    ("red and green swapped", [("RG[p] += (sum[p] << 32) + sum[npix + p];", "RG[p] += (sum[npix + p] << 32) + sum[p];")],
+     []),
+    ("count of two", [("sum[3 * npix + pid] += 1;", "sum[3 * npix + pid] += 2;")], []),
+    ("green from the red half", [("RG[p] & 0xFFFFFFFFull, BA[p] >> 32", "RG[p] >> 32, BA[p] >> 32")], []),
+    ("hq alpha 0", [("uint32_t colour = 0xFF000000u;", "uint32_t colour = 0u;")], []),
+    ("blue from the green byte", [("sum[c * npix + pid] += (pts[i].rgba >> (8 * c)) & 0xFFu;",
+                                   "sum[c * npix + pid] += (pts[i].rgba >> (8 * (c ? 1 : 0))) & 0xFFu;")], []),
     ("morton y/z swapped", [("<< (3 * i + 1);", "<< (3 * i + 9999);"), ("<< (3 * i + 2);", "<< (3 * i + 1);"),
                             ("<< (3 * i + 9999);", "<< (3 * i + 2);")], []),
     ("morton 2^21 - 1 scale", [("* 2097152.0f", "* 2097151.0f")], []),
