@@ -442,8 +442,9 @@ def leg_hq(args):
     img = torch.empty(W * H, dtype=torch.int32, device="cuda")
     out, images = {}, {}
     for name, var in (("hq", pcr.HQ), ("hq_plain", pcr.HQ | pcr.F_PLAIN), ("hq_packed", pcr.HQ | pcr.F_HQ_PACKED),
-                      ("hq_packed_plain", pcr.HQ | pcr.F_HQ_PACKED | pcr.F_PLAIN), ("dedup", pcr.DEDUP),
-                      ("basic", pcr.BASIC)):
+                      ("hq_packed_plain", pcr.HQ | pcr.F_HQ_PACKED | pcr.F_PLAIN),
+                      ("hq_robust", pcr.HQ | pcr.F_HQ_ROBUST), ("hq_robust_plain", pcr.HQ | pcr.F_HQ_ROBUST | pcr.F_PLAIN),
+                      ("dedup", pcr.DEDUP), ("basic", pcr.BASIC)):
         fb = pcr.alloc_fb(W, H, var)
 
         def frame():
@@ -461,6 +462,9 @@ def leg_hq(args):
     # 1023 points blended into them)
     out["hq_packed"]["pixels_differing_from_hq"] = int((images["hq_packed"] != images["hq"]).sum())
     out["hq_packed"]["plain_same_image"] = bool(torch.equal(images["hq_packed"], images["hq_packed_plain"]))
+    # the robust form equals the two-word form on every pixel
+    out["hq_robust"]["same_image_as_hq"] = bool(torch.equal(images["hq_robust"], images["hq"]))
+    out["hq_robust_plain"]["same_image_as_hq"] = bool(torch.equal(images["hq_robust_plain"], images["hq"]))
     return {"metric": METRIC, "value": out["hq"]["Gpts_s"], "unit": "Gpts/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": out["hq"]["frame_ms"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+u64",
@@ -538,8 +542,11 @@ def batch_views(count, seed=5):
 def leg_batch(args):
     """64 camera views of one 145M-point cloud (100M terrain + 45M buildings,
     shuffled Morton), framebuffers 1280x720 / 1920x1080 / 3840x2160, basic and
-    HQ alternating: one autotuned batch plan (single hipGraph replay) against
-    64 single-view renders in sequence; outputs compared for identity."""
+    HQ alternating: one batch plan (a single hipGraph replay) in its default
+    shape (grouped passes: each tile of points loaded once per group of views)
+    against 64 single-view renders in sequence with the same kernels, and the
+    plan's per-view form; outputs compared for identity.  --tune also runs the
+    autotuner over the plan shapes (not part of the default run)."""
     import torch
     from paper_2104_07526_amd import pcr, synth, tune
     nt, nb = 100_000_000, 45_000_000
@@ -563,19 +570,30 @@ def leg_batch(args):
     log("batch leg: sequential single-view renders")
     seq_best = time_frames(lambda: sequential(True), max(1, args.steps // 2), 1)
     seq_plain = time_frames(lambda: sequential(False), 1, 0)
-    log("batch leg: autotuning the plan")
-    pviews = [pcr.make_view(m, W, H, var, fb, im) for (m, W, H, var), fb, im in zip(views, fbs, imgs)]
-    best_tune, table = tune.tune_batch(d, pviews, reps=2)
-    log(f"batch leg: timing the tuned plan {best_tune}")
-    plan = pcr.BatchPlan(d, len(pviews), tune=best_tune)
-    bms = time_frames(lambda: plan.launch(pviews), args.steps, args.warmup)
-    torch.cuda.synchronize()
     sequential(True)
     torch.cuda.synchronize()
-    plan.launch(pviews)
-    torch.cuda.synchronize()
-    same = all(torch.equal(a, b) for a, b in zip(imgs, ref))
-    plan.close()
+    pviews = [pcr.make_view(m, W, H, var, fb, im) for (m, W, H, var), fb, im in zip(views, fbs, imgs)]
+    out = {}
+    for name, shape in (("default", None), ("per_view", {"group": 1})):
+        plan = pcr.BatchPlan(d, len(pviews), tune=shape)
+        ms = time_frames(lambda: plan.launch(pviews), args.steps, args.warmup)
+        for im in imgs:
+            im.fill_(0)
+        plan.launch(pviews)
+        torch.cuda.synchronize()
+        same = all(torch.equal(a, b) for a, b in zip(imgs, ref))
+        plan.close()
+        out[name] = {"ms": round(ms, 3), "identical_images": bool(same), "speedup_vs_sequential": round(seq_best / ms, 3)}
+        log(f"batch leg: {name} plan {out[name]}")
+    table = None
+    if args.tune:
+        log("batch leg: autotuning the plan")
+        best_tune, table = tune.tune_batch(d, pviews, reps=2, use_cache=False)
+        plan = pcr.BatchPlan(d, len(pviews), tune=best_tune)
+        ms = time_frames(lambda: plan.launch(pviews), args.steps, args.warmup)
+        plan.close()
+        out["tuned"] = {"ms": round(ms, 3), "tune": best_tune, "speedup_vs_sequential": round(seq_best / ms, 3)}
+    bms = out["default"]["ms"]
     pv = n * len(views)
     return {"metric": METRIC, "value": round(pv / bms / 1e6, 2), "unit": "Gpts/s (point-views)", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(bms, 3), "higher_is_better": True,
@@ -583,19 +601,18 @@ def leg_batch(args):
             "config": {"workload": "145M points (terrain 100M + buildings 45M), shuffled Morton; 64 views, "
                                    "1280x720/1920x1080/3840x2160 cycling, basic/HQ alternating; one batch "
                                    "= clear + render + resolve of all 64 views", "points": n, "views": 64},
-            "detail": {"batched_ms": round(bms, 3), "sequential_best_ms": round(seq_best, 3),
-                       "sequential_plain_ms": round(seq_plain, 3),
-                       "speedup_vs_sequential_best": round(seq_best / bms, 3),
-                       "speedup_vs_sequential_plain": round(seq_plain / bms, 3),
-                       "identical_images": bool(same), "tune": best_tune, "tune_table": table[:8],
-                       "reorder_ms": round(rms, 2)}}
+            "detail": {"plans": out, "sequential_ms": round(seq_best, 3),
+                       "speedup_vs_sequential": out["default"]["speedup_vs_sequential"],
+                       "sequential_note": "64 single-view renders, one after another, with the same kernels as "
+                                          "the plan (dedup for basic views, the merged HQ passes)",
+                       "sequential_atomicmin_ms": round(seq_plain, 3),
+                       "tune_table": table[:8] if table else None, "reorder_ms": round(rms, 2)}}
 
 
-# Server policy of the serve leg (picked by sweeps on this load): batches that
-# stream at least SERVE_BIG_POINTS points run one at a time (150M-1000M
-# swept), a batch holds at most that many points x views, and at most
-# SERVE_SMALL_BESIDE_BIG smaller batches run beside a large one (0, 2, 4 and
-# no limit swept).
+# The earlier server policy, kept as the "overlap" comparison of the serve
+# leg: batches that stream at least SERVE_BIG_POINTS points run one at a time,
+# a batch holds at most that many points x views, and at most
+# SERVE_SMALL_BESIDE_BIG smaller batches run beside a large one.
 SERVE_BIG_POINTS = 250_000_000
 SERVE_SMALL_BESIDE_BIG = 2
 
@@ -735,11 +752,21 @@ def leg_serve(args):
     at fractions of the one-at-a-time service rate; continuous-batching server
     against a one-at-a-time server on the same arrival sequence."""
     sizes, clouds = serve_clouds(args)
-    policy = {"max_batch_points": SERVE_BIG_POINTS, "big_points": SERVE_BIG_POINTS,
-              "small_beside_big": SERVE_SMALL_BESIDE_BIG}
-    svc, rates = serve_measure(args, clouds, {"batched": ({}, policy)})
+    # The server: GpuBackend's defaults (two streams, one plan per cloud, no
+    # cap on a batch's points), so that the requests of a cloud gather behind
+    # its running batch and share the next one's point stream.  "overlap" is
+    # the earlier policy: eight streams, two plans per cloud, batches capped
+    # at SERVE_BIG_POINTS points x views, large batches one at a time.
+    overlap = ({"streams": 8, "plans_per_cloud": 2},
+               {"max_batch_points": SERVE_BIG_POINTS, "big_points": SERVE_BIG_POINTS,
+                "small_beside_big": SERVE_SMALL_BESIDE_BIG})
+    servers = {"batched": ({}, {}), "overlap": overlap}
+    if args.serve_variants:
+        servers["shared_3x1"] = ({"streams": 3, "plans_per_cloud": 1}, {})
+        servers["shared_4x2"] = ({"streams": 4, "plans_per_cloud": 2}, {})
+    svc, rates = serve_measure(args, clouds, servers)
     # framebuffer budget sweep at the one-at-a-time rate (same policy)
-    _, sweep = serve_measure(args, clouds, {f"budget_{b >> 20}MB": ({"budget_bytes": b}, policy)
+    _, sweep = serve_measure(args, clouds, {f"budget_{b >> 20}MB": ({"budget_bytes": b}, {})
                                             for b in (512 << 20, 8 << 30)}, fracs=(1.0,), seed=7)
     top = rates["1.00"]
     return {"metric": METRIC, "value": top["batched"]["Gpts_s"], "unit": "Gpts/s", "n_gpus": 1,
@@ -752,7 +779,7 @@ def leg_serve(args):
                        "requests_per_rate": args.requests},
             "detail": {"service_ms_one_at_a_time": round(1e3 * svc, 3), "rates": rates,
                        "budget_sweep_at_1.0": sweep["1.00"],
-                       "server": {"streams": 8, **policy},
+                       "server": {"streams": 2, "plans_per_cloud": 1, "plan": "grouped passes (default shape)"},
                        "p50_ms_at_1.0": top["batched"]["p50_ms"], "p99_ms_at_1.0": top["batched"]["p99_ms"]}}
 
 
@@ -1110,6 +1137,8 @@ def main():
                                                         "serve", "calib", "lod", "resolve", "techniques"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-terrain", action="store_true", help="default leg: skip the terrain frames")
+    ap.add_argument("--tune", action="store_true", help="batch leg: also run the plan autotuner")
+    ap.add_argument("--serve-variants", action="store_true", help="serve leg: also measure other server policies")
     ap.add_argument("--requests", type=int, default=2000, help="requests per arrival rate (serve leg)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

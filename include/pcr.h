@@ -154,13 +154,17 @@ enum {
  *   group  views per point pass in a batch (0 = all that fit the cache budget;
  *          1 = every view its own pass with the single-view kernels)
  *   slots  LDS hash-table slots per workgroup of the deduplicating kernels,
- *          rounded up to a power of two in [256, 32768] (0 = half a tile) */
+ *          rounded up to a power of two in [256, 32768] (0 = half a tile)
+ *   run    basic kernel (PCR_BASIC without flags): consecutive points per lane,
+ *          a multiple of ppt up to 4096, taken ppt at a time (0 = ppt); one
+ *          atomic instruction then covers points `run` apart */
 typedef struct pcr_tune {
     uint32_t ppt;
     uint32_t wg;
     uint32_t grid;
     uint32_t group;
     uint32_t slots;
+    uint32_t run;
 } pcr_tune;
 
 /* Framebuffer layout (device memory, size pcr_fb_bytes):

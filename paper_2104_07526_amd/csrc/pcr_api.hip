@@ -68,13 +68,16 @@ int resolve_shape(const pcr_tune *tune, int family, Shape &s) {
     s.grid = (basic ? 64u : 512u) * (uint32_t)device_cus();
     s.group = 0;
     s.slots = 0;
+    s.run = 0;
     if (tune) {
         if (tune->wg) s.wg = tune->wg;
         if (tune->ppt) s.ppt = tune->ppt;
         if (tune->grid) s.grid = tune->grid;
         s.group = tune->group;
         s.slots = tune->slots;
+        s.run = tune->run;
     }
+    if (s.run > 4096 || s.run % s.ppt) return fail(PCR_EINVAL, "run %u is not a multiple of ppt %u up to 4096", s.run, s.ppt);
     if (s.slots > 32768) return fail(PCR_EINVAL, "slots %u above 32768", s.slots);
     if (!pow2_in(s.wg, 64, 1024)) return fail(PCR_EINVAL, "workgroup size %u is not a power of two in [64, 1024]", s.wg);
     if (!pow2_in(s.ppt, 1, 16)) return fail(PCR_EINVAL, "points per thread %u is not 1, 2, 4, 8 or 16", s.ppt);

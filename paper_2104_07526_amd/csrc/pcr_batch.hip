@@ -6,13 +6,13 @@
 //   pass A  closest-point views (basic / dedup) and the depth pass of HQ views
 //   pass B  the colour pass of HQ views (needs every HQ depth complete)
 //   resolve all views
-// In the batched form, passes A and B are one kernel each: workgroups step
+// In the grouped form, passes A and B are one kernel each: workgroups step
 // over (group, tile) items in group-major order, load the tile's points once
-// and render them into every view of the group, deduplicating same-pixel
-// updates in a shared LDS table.  Views are grouped so that a group's
-// framebuffers fit the cache budget, which keeps the atomics of a pass inside
-// a small, cache-resident working set while the point stream is read once per
-// group.  In the per-view form (tune group 1) every view slot runs the
+// and render them into every view of the group in turn with the single-view
+// kernels' tile body, so the point stream is read once per group instead of
+// once per view.  Views are grouped so that a group's framebuffers fit the
+// cache budget, which keeps the atomics of a pass inside a cache-resident
+// working set.  In the per-view form (tune group 1) every view slot runs the
 // single-view passes instead, reading its view from the device table; slots a
 // launch does not use are disabled in the graph.  Every update is an integer
 // min or sum, so each view is bit-identical to rendering it alone.
@@ -27,14 +27,12 @@
 namespace pcr {
 namespace {
 
-constexpr uint32_t kBatchWg = 256;
 constexpr uint64_t kGroupBudget = 160ull << 20;  // framebuffer bytes per group
+constexpr uint32_t kMaxGroup = 32;                // views per group
+constexpr uint32_t kPidMask = (1u << 27) - 1u;    // largest pixel count of a batched view
 
 using DevView = BatchView;
-
-struct Group {
-    uint32_t first, count;  // range of the pass's view-index list
-};
+using Group = BatchGroup;
 
 // Device table: header, then groups and index lists of both passes, then views.
 struct Header {
@@ -130,227 +128,7 @@ __global__ __launch_bounds__(256) void k_batch_resolve(const unsigned char *base
     }
 }
 
-// ---------------------------------------------------------------------------
-// Persistent multi-view passes
-// ---------------------------------------------------------------------------
-constexpr uint32_t kMaxProbeB = 8;
 
-__device__ __forceinline__ void bar_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-// LDS: item | count | val[HS] (16 B: min key, or RG and BA sums) | tag[HS] | list[HS]
-struct BLds {
-    uint32_t *item, *count, *tag, *list;
-    u64 *val;  // 2 words per slot
-    uint32_t mask, shift;
-    __device__ BLds(unsigned char *sm, uint32_t hbits) {
-        item = (uint32_t *)sm;
-        count = item + 1;
-        val = (u64 *)(sm + 16);
-        tag = (uint32_t *)(val + 2 * (1u << hbits));
-        list = tag + (1u << hbits);
-        mask = (1u << hbits) - 1u;
-        shift = 24u - hbits;  // hbits <= 15: the top bits of a 24-bit product
-    }
-    // Home slot of a (view slot, pixel) tag: the view bits are folded into
-    // the low 24 bits, then Fibonacci hashing in a 24-bit word (full-rate
-    // 24-bit multiply; __umul24 returns a signed int: shifted as unsigned and
-    // masked into the table).
-    __device__ __forceinline__ uint32_t home(uint32_t key) const {
-        const uint32_t k = (key ^ (key >> 20)) & 0xFFFFFFu;
-        return ((uint32_t)__umul24(k, 0x9E3779u) >> shift) & mask;
-    }
-    __device__ __forceinline__ uint32_t slot(uint32_t pid) {
-        uint32_t h = home(pid);
-#pragma unroll 1
-        for (uint32_t probe = 0; probe < kMaxProbeB; ++probe) {
-            uint32_t t = __hip_atomic_load(tag + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (t == pid) return h;
-            if (t == kEmptyPid) {
-                uint32_t old = atomicCAS(tag + h, kEmptyPid, pid);
-                if (old == kEmptyPid) {
-                    list[atomicAdd(count, 1u)] = h;
-                    return h;
-                }
-                if (old == pid) return h;
-            }
-            h = (h + 1u) & mask;
-        }
-        return 0xFFFFFFFFu;
-    }
-};
-
-__device__ __forceinline__ void lmin64(u64 *p, u64 v) {
-    u64 cur = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (v < cur) __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-// One LDS table serves all views of a group: its tag packs the view's slot in
-// the group (5 bits) above the pixel index (27 bits).  A tile is projected into
-// every view of its group in turn; the table is flushed to the framebuffers
-// only when it is half full and at the end of the tile.
-constexpr uint32_t kPidBits = 27;
-constexpr uint32_t kPidMask = (1u << kPidBits) - 1u;
-constexpr uint32_t kMaxGroup = 32;
-
-// PASS = 0: closest-point views (64-bit keys) and HQ depth (depth bits);
-// PASS = 1: HQ colour sums.
-template <int PPT, int PASS>
-__global__ __launch_bounds__(kBatchWg) void k_batch_pass(const u32x4 *__restrict__ pts, uint64_t n,
-                                                         unsigned char *base, TableLayout L, uint32_t hbits) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    // The group's views, staged once per item: camera and viewport, buffers.
-    __shared__ View vpar[kMaxGroup];
-    __shared__ u64 vbuf[kMaxGroup][2];  // per group slot: fb (or D) and S
-    __shared__ uint32_t vhq[kMaxGroup];
-    BLds S(smem, hbits);
-    Table t = table(base, L);
-    const uint32_t HS = 1u << hbits;
-    const uint32_t wg = blockDim.x;  // 64, 128 or 256
-    const uint32_t T = wg * PPT;
-    const uint64_t ntiles = (n + T - 1) / T;
-    for (uint32_t s = threadIdx.x; s < HS; s += wg) {
-        S.tag[s] = kEmptyPid;
-        S.val[2 * s] = PASS ? 0ull : kEmptyKey;
-        S.val[2 * s + 1] = 0ull;
-    }
-    if (threadIdx.x == 0) *S.count = 0;
-    bar_lds();
-
-    // Writes the table's entries to their views' buffers and empties it.
-    auto flush = [&]() {
-        bar_lds();
-        const uint32_t cnt = *S.count;
-        bar_lds();
-        if (threadIdx.x == 0) *S.count = 0;
-        for (uint32_t k = threadIdx.x; k < cnt; k += wg) {
-            uint32_t h = S.list[k];
-            uint32_t tag = S.tag[h];
-            uint32_t vs = tag >> kPidBits, pid = tag & kPidMask;
-            u64 a = S.val[2 * h], b = S.val[2 * h + 1];
-            S.tag[h] = kEmptyPid;
-            S.val[2 * h] = PASS ? 0ull : kEmptyKey;
-            S.val[2 * h + 1] = 0ull;
-            if (PASS == 0) {
-                if (vhq[vs]) {
-                    // Early test: any value the word has held is >= its
-                    // current one, so a stale read never skips a needed update.
-                    uint32_t *D = (uint32_t *)vbuf[vs][0];
-                    const uint32_t seen = __hip_atomic_load(D + pid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    if ((uint32_t)a < seen) gmin_u32(D + pid, (uint32_t)a);
-                } else {
-                    gmin_u64((u64 *)vbuf[vs][0] + pid, a);
-                }
-            } else {
-                u64 *Sm = (u64 *)vbuf[vs][1];
-                gadd_u64(Sm + 2 * (u64)pid, a);
-                gadd_u64(Sm + 2 * (u64)pid + 1, b);
-            }
-        }
-        bar_lds();
-    };
-
-    // Grid-stride over the (group, tile) items in group-major order with the
-    // tiles in their natural order (no shared queue: same-address atomics
-    // serialise at the memory-side atomic unit): the workgroups resident at
-    // one time work on one window of the point order, the schedule that the
-    // single-view kernels measured fastest.  A workgroup's items stay in one
-    // group for ntiles / grid items, so its views are restaged only when the
-    // group changes.
-    const uint32_t ngroups = t.h->ngroups[PASS];
-    const uint64_t nitems = (uint64_t)ngroups * ntiles;
-    uint32_t cur_g = 0xFFFFFFFFu, gcount = 0;
-    for (uint64_t item = blockIdx.x; item < nitems; item += gridDim.x) {  // uniform exit for every workgroup
-        const uint32_t g = (uint32_t)(item / ntiles);
-        const uint64_t tile = item - (uint64_t)g * ntiles;
-        const uint64_t first = tile * T;
-        const uint64_t rem = n - first;
-        u32x4 p[PPT];
-#pragma unroll
-        for (int j = 0; j < PPT; ++j) {
-            uint32_t k = (uint32_t)(j * wg + threadIdx.x);
-            p[j] = load_point(pts + first + (k < rem ? k : (uint32_t)(rem - 1)));
-        }
-        if (g != cur_g) {
-            const Group grp = t.groups[PASS][g];
-            gcount = (uint32_t)__builtin_amdgcn_readfirstlane((int)grp.count);
-            if (threadIdx.x < gcount) {
-                const DevView &dv = t.views[t.index[PASS][grp.first + threadIdx.x]];
-                vpar[threadIdx.x] = dv.v;
-                vhq[threadIdx.x] = dv.variant == PCR_HQ;
-                vbuf[threadIdx.x][0] = (u64)(dv.variant == PCR_HQ ? (void *)dv.D : (void *)dv.fb);
-                vbuf[threadIdx.x][1] = (u64)dv.S;
-            }
-            cur_g = g;
-            bar_lds();
-        }
-        for (uint32_t vs = 0; vs < gcount; ++vs) {
-            const View v = vpar[vs];
-            const bool hq = vhq[vs] != 0;
-            u64 *const fbv = (u64 *)vbuf[vs][0];
-            uint32_t *const Dv = (uint32_t *)vbuf[vs][0];
-            u64 *const Sv = (u64 *)vbuf[vs][1];
-            uint32_t pids[PPT], dbs[PPT];
-#pragma unroll
-            for (int j = 0; j < PPT; ++j)
-                pids[j] = project_wave(v, p[j], (uint64_t)(j * wg + threadIdx.x) < rem, dbs[j]);
-            if (PASS == 0) {
-#pragma unroll
-                for (int j = 0; j < PPT; ++j) {
-                    const uint32_t pid = pids[j];
-                    if (pid == kEmptyPid) continue;
-                    const uint32_t key = (vs << kPidBits) | pid;
-                    u64 val = hq ? (u64)dbs[j] : make_key(dbs[j], p[j].w);
-                    uint32_t h = S.slot(key);
-                    if (h != 0xFFFFFFFFu) {
-                        lmin64(S.val + 2 * h, val);
-                    } else if (hq) {
-                        gmin_u32(Dv + pid, dbs[j]);
-                    } else {
-                        gmin_u64(fbv + pid, val);
-                    }
-                }
-            } else {
-                // All closest-depth reads of the tile back to back, then the sums.
-                uint32_t dref[PPT];
-#pragma unroll
-                for (int j = 0; j < PPT; ++j) dref[j] = Dv[pids[j] != kEmptyPid ? pids[j] : 0u];
-#pragma unroll
-                for (int j = 0; j < PPT; ++j) {
-                    const uint32_t pid = pids[j];
-                    if (pid == kEmptyPid) continue;
-                    if (!(__uint_as_float(dbs[j]) <= __uint_as_float(dref[j]) * 1.01f)) continue;
-                    const uint32_t key = (vs << kPidBits) | pid;
-                    u64 r = p[j].w & 0xFFu, gg = (p[j].w >> 8) & 0xFFu, bl = (p[j].w >> 16) & 0xFFu;
-                    u64 rg = (r << 32) | gg, ba = (bl << 32) | 1u;
-                    uint32_t h = S.slot(key);
-                    if (h != 0xFFFFFFFFu) {
-                        __hip_atomic_fetch_add(S.val + 2 * h, rg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        __hip_atomic_fetch_add(S.val + 2 * h + 1, ba, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    } else {
-                        gadd_u64(Sv + 2 * (u64)pid, rg);
-                        gadd_u64(Sv + 2 * (u64)pid + 1, ba);
-                    }
-                }
-            }
-            // Flush early when the table is half full.  The decision must be
-            // the same in every wave: all waves read the count between two
-            // barriers, so none inserts again before all have read it.
-            if (vs + 1 < gcount) {
-                bar_lds();
-                const uint32_t fill = (uint32_t)__builtin_amdgcn_readfirstlane((int)*S.count);
-                bar_lds();
-                if (fill > HS / 2) flush();
-            }
-        }
-        flush();
-    }
-}
-
-inline size_t batch_lds(uint32_t hbits) { return 16 + 24ull * (1u << hbits); }
 
 }  // namespace
 
@@ -364,7 +142,6 @@ struct pcr_batch {
     uint64_t n = 0;
     uint32_t capacity = 0;
     pcr::Shape sh{};
-    uint32_t hbits = 10;
     pcr::TableLayout lay{};
     unsigned char *dtable = nullptr;
     static constexpr int kRing = 4;
@@ -375,7 +152,7 @@ struct pcr_batch {
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    uint32_t grid_pass[2] = {0, 0}, grid_io = 0;
+    uint32_t grid_io = 0;
     // Per-view mode: the graph node of each (pass, slot) and whether it is
     // enabled in `exec`; slots a launch does not use are disabled, so they
     // cost no dispatch.
@@ -386,52 +163,15 @@ struct pcr_batch {
 namespace pcr {
 namespace {
 
-// Workgroups of a batched pass without a set grid: as many as are resident at
-// once on the device, so that no workgroup waits for another to finish its
-// whole share.
-int resident_grid(const void *fn, uint32_t wg, size_t sm, uint32_t &grid) {
-    int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, (int)wg, sm);
-    if (e != hipSuccess || per_cu <= 0) return fail(PCR_EHIP, "occupancy query failed: %s", hipGetErrorString(e));
-    grid = (uint32_t)per_cu * (uint32_t)device_cus();
-    return PCR_OK;
-}
-
-// Workgroups of a batched pass: the plan's grid, or as many as are resident.
-int pass_grid(const void *fn, const pcr_batch *b, size_t sm, uint32_t &grid) {
-    if (b->sh.grid) {
-        grid = b->sh.grid;
-        return PCR_OK;
-    }
-    return resident_grid(fn, b->sh.wg, sm, grid);
-}
-
+// Grouped pass `pass` over the plan's table (pass < 0: only raise the
+// kernels' LDS limits, done before graph capture).
 int launch_pass(pcr_batch *b, int pass, hipStream_t s) {
-    // pass < 0: only raise the kernels' LDS limit (done before graph capture).
-    size_t sm = batch_lds(b->hbits);
-#define PCR_BP(P)                                                                                      \
-    case P:                                                                                            \
-        if (pass < 0) {                                                                                \
-            int rc = allow_lds((const void *)&k_batch_pass<P, 0>, sm);                                 \
-            if (rc == PCR_OK) rc = allow_lds((const void *)&k_batch_pass<P, 1>, sm);                   \
-            if (rc == PCR_OK) rc = pass_grid((const void *)&k_batch_pass<P, 0>, b, sm, b->grid_pass[0]);     \
-            if (rc == PCR_OK) rc = pass_grid((const void *)&k_batch_pass<P, 1>, b, sm, b->grid_pass[1]);     \
-            return rc;                                                                                 \
-        }                                                                                              \
-        if (pass)                                                                                      \
-            hipLaunchKernelGGL((k_batch_pass<P, 1>), dim3(b->grid_pass[1]), dim3(b->sh.wg), sm, s, b->pts, b->n, \
-                               b->dtable, b->lay, b->hbits);                                           \
-        else                                                                                           \
-            hipLaunchKernelGGL((k_batch_pass<P, 0>), dim3(b->grid_pass[0]), dim3(b->sh.wg), sm, s, b->pts, b->n, \
-                               b->dtable, b->lay, b->hbits);                                           \
-        break;
-    switch (b->sh.ppt) {
-        PCR_BP(1) PCR_BP(2) PCR_BP(4) PCR_BP(8) PCR_BP(16)
-        default: return fail(PCR_EINVAL, "points per thread %u", b->sh.ppt);
-    }
-#undef PCR_BP
-    PCR_LAUNCHED();
-    return PCR_OK;
+    const BatchView *views = (const BatchView *)(b->dtable + b->lay.views);
+    const int p = pass < 0 ? 0 : pass;
+    const uint32_t *index = (const uint32_t *)(b->dtable + b->lay.index[p]);
+    const BatchGroup *groups = (const BatchGroup *)(b->dtable + b->lay.groups[p]);
+    const uint32_t *ng = (const uint32_t *)(b->dtable + offsetof(Header, ngroups) + sizeof(uint32_t) * p);
+    return launch_group_pass(pass, b->pts, b->n, views, index, groups, ng, b->sh, s);
 }
 
 // Per-view mode (group 1): every view slot gets the single-view passes; a
@@ -512,10 +252,6 @@ extern "C" int pcr_batch_create(pcr_batch **plan, const pcr_point *pts, uint64_t
     if (n == 0 || !pts || ((uintptr_t)pts & 15)) return fail(PCR_EINVAL, "points must be a non-empty 16-byte aligned device buffer");
     pcr_tune t{};
     if (tune) t = *tune;
-    if (t.group != 1) {  // the batched pass runs 64-, 128- or 256-thread workgroups
-        if (t.wg == 0) t.wg = kBatchWg;
-        if (t.wg > kBatchWg) return fail(PCR_EINVAL, "batched passes take at most %u threads per workgroup", kBatchWg);
-    }
     Shape sh;
     int rc = resolve_shape(&t, PCR_DEDUP, sh);
     if (rc != PCR_OK) return rc;
@@ -524,13 +260,6 @@ extern "C" int pcr_batch_create(pcr_batch **plan, const pcr_point *pts, uint64_t
     b->n = n;
     b->capacity = capacity;
     b->sh = sh;
-    uint32_t want = sh.slots ? sh.slots : sh.wg * sh.ppt / 2;
-    b->hbits = 8;
-    while ((1u << b->hbits) < want && b->hbits < 14) ++b->hbits;
-    if (batch_lds(b->hbits) > max_lds()) {
-        destroy(b);
-        return fail(PCR_EINVAL, "%u LDS slots do not fit", 1u << b->hbits);
-    }
     b->lay = layout(capacity);
     b->grid_io = (uint32_t)device_cus() * 16;
     hipError_t e = hipMalloc((void **)&b->dtable, b->lay.bytes);
@@ -558,8 +287,7 @@ extern "C" int pcr_batch_create(pcr_batch **plan, const pcr_point *pts, uint64_t
         destroy(b);
         return fail(PCR_EHIP, "plan set-up failed");
     }
-    rc = launch_pass(b, -1, nullptr);
-    if (rc == PCR_OK && b->sh.group == 1) rc = view_passes(b, -1, nullptr);
+    rc = b->sh.group == 1 ? view_passes(b, -1, nullptr) : launch_pass(b, -1, nullptr);
     if (rc != PCR_OK) {
         destroy(b);
         return rc;
@@ -679,7 +407,8 @@ uint64_t g_cache_tick = 0;
 constexpr size_t kCachedPlans = 8;
 
 bool same_tune(const pcr_tune &a, const pcr_tune &b) {
-    return a.ppt == b.ppt && a.wg == b.wg && a.grid == b.grid && a.group == b.group && a.slots == b.slots;
+    return a.ppt == b.ppt && a.wg == b.wg && a.grid == b.grid && a.group == b.group && a.slots == b.slots &&
+           a.run == b.run;
 }
 
 }  // namespace

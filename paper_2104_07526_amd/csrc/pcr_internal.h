@@ -183,6 +183,7 @@ struct Shape {
     uint32_t ppt, wg, grid;
     uint32_t group;  // views per point pass (batches)
     uint32_t slots;  // LDS hash slots of the deduplicating kernels (0 = tile/2)
+    uint32_t run;    // basic kernel: consecutive points per lane (a multiple of ppt)
 };
 int resolve_shape(const pcr_tune *tune, int family, Shape &s);
 
@@ -199,6 +200,18 @@ struct BatchView {
     u64 *S;           // HQ sums
     uint32_t *out;
 };
+
+// A group of a batch pass: views index[first .. first + count) of the table.
+struct BatchGroup {
+    uint32_t first, count;
+};
+
+// Grouped pass of a batch (pass 0: closest-point views and HQ depth passes;
+// pass 1: HQ colour passes): each tile of the points is loaded once per group
+// and rendered into the group's views in turn.  *ngroups and the tables are
+// read when the kernel runs.  pass < 0 only raises the kernels' LDS limits.
+int launch_group_pass(int pass, const u32x4 *pts, uint64_t n, const BatchView *views, const uint32_t *index,
+                      const BatchGroup *groups, const uint32_t *ngroups, const Shape &sh, hipStream_t s);
 
 // Single-view render pass of batch slot `slot`, read from a plan's device
 // table when the kernel runs (nothing happens if slot >= *nviews): pass 0 the

@@ -7,6 +7,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 
 #include "pcr_internal.h"
 
@@ -280,6 +281,7 @@ inline uint32_t lds_hbits(uint32_t T, uint32_t group) {
 // resident at one time work on one window of the point order).
 struct Tiles {
     uint64_t n, ntiles, nblocks;
+    uint32_t run;  // basic kernel: consecutive points per lane
     __device__ __forceinline__ bool tile(uint64_t b, uint64_t &t) const {
         t = b;
         return t < ntiles;
@@ -390,48 +392,95 @@ struct ChunkSrc {
 
 // Basic closest-point render (Sec. 3.1), optionally with the early depth test
 // (Sec. 3.2) and the wavefront reduction (Sec. 3.3).
+//
+// Lane mapping.  With the wavefront reduction (which merges neighbouring
+// lanes) and for chunked frames, an instruction's lanes take consecutive
+// points.  Otherwise each wavefront takes a sub-tile of 64 * run consecutive
+// points, PPT per lane per step, in one of two mappings:
+//   runs       lane l walks the points [l*run, (l+1)*run) of the sub-tile;
+//   interleaved step c covers the points [c*64*PPT, (c+1)*64*PPT), lane l
+//              taking PPT consecutive ones.
+// The same atomics land differently: where consecutive points fall on one
+// pixel (distant views, many points per pixel) the interleaved mapping puts
+// many lanes of an instruction on one address, which the memory-side atomic
+// unit serialises, while runs spread them over distinct pixels; where
+// consecutive points fall on neighbouring pixels, the interleaved mapping
+// keeps an instruction's atomics on few 64-byte lines, which the unit takes
+// in one request each.  tl.run > 0 fixes runs of that length (run == PPT is
+// both mappings); tl.run == 0 adapts per wavefront and sub-tile of 64 *
+// kAdaptRun points: the first step is interleaved, and the rest of the
+// sub-tile goes in runs (of kAdaptRun - PPT points) when in that first step
+// more neighbouring lanes (points PPT apart) landed on one pixel than on two
+// pixels of one 64-byte line, else interleaved: same-pixel atomics favour
+// runs, same-line ones the interleaved mapping.  (Measured against fixed
+// mappings and other rules on three vertex orders and three poses of the
+// terrain and on the 796M frame: within 9% of the best fixed mapping in every
+// case and best summed over them.)
+constexpr uint32_t kAdaptRun = 32;
+
 template <int PPT, bool EARLYZ, bool REDUCE, class Src>
 __global__ __launch_bounds__(1024) void k_basic(const u32x4 *__restrict__ pts, Tiles tl, View v,
                                                 u64 *__restrict__ fb, Src src) {
     const uint32_t wg = blockDim.x;
     if constexpr (Src::chunked) src.setup(tl, wg * PPT);
-    // Without the wavefront reduction (which merges neighbouring lanes), a
-    // lane takes PPT consecutive points of a flat buffer: the 64 atomics of
-    // one instruction then fall on points PPT apart, so fewer of them meet on
-    // one pixel, and a lane's run of (often same-pixel) points is spread over
-    // PPT instructions.  Same atomics, fewer collisions (measured 16-30%
-    // faster on every vertex order).
-    constexpr bool kRuns = !REDUCE && !Src::chunked;
+    constexpr bool kSub = !REDUCE && !Src::chunked;
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const bool adapt = kSub && tl.run == 0;
+    const uint32_t run = !kSub ? PPT : (adapt ? kAdaptRun : tl.run);
     for (uint64_t b = blockIdx.x; b < tl.nblocks; b += gridDim.x) {
         uint64_t t;
         if (!src.tile(tl, b, t)) continue;
-        u32x4 p[PPT];
-        // lim: points of the tile (uniform; 32-bit compares).
-        uint32_t lim;
-        if constexpr (kRuns) {
-            const uint64_t first = t * wg * PPT, rem = tl.n - first;
-            lim = rem < (uint64_t)wg * PPT ? (uint32_t)rem : wg * PPT;
-            // Cached loads: the PPT loads of a run touch each line PPT times
-            // (non-temporal loads would fetch it again from HBM each time).
-            const u32x4 *tp = pts + first;
+        // sub: points of this wavefront's sub-tile (uniform; 32-bit compares).
+        uint32_t sub = 0;
+        const u32x4 *tp = pts;
+        if constexpr (kSub) {
+            const uint64_t first = t * wg * run + (uint64_t)wave * 64u * run;
+            const uint64_t rem = first < tl.n ? tl.n - first : 0;
+            sub = rem < 64ull * run ? (uint32_t)rem : 64u * run;
+            tp = pts + first;
+            if (sub == 0) continue;  // the last tile ends before this wavefront's part
+        }
+        bool runs = !adapt;           // adaptive: decided after the first step
+        // neighbouring lanes whose visible points share a pixel / share only a 64-byte line
+        uint32_t same = 0, line = 0;
+#pragma unroll 1
+        for (uint32_t c = 0; c < run; c += PPT) {
+            u32x4 p[PPT];
+            uint32_t k0 = 0;  // index of the lane's first point of this step in the sub-tile
+            uint32_t lim = sub;
+            if constexpr (kSub) {
+                if (!adapt) k0 = lane * run + c;
+                else if (c == 0 || !runs) k0 = c * 64u + lane * PPT;
+                else k0 = 64u * PPT + lane * (run - PPT) + (c - PPT);
+                // Cached loads: a lane's PPT consecutive loads touch each line
+                // several times (non-temporal loads would fetch it again).
+#pragma unroll
+                for (int j = 0; j < PPT; ++j) {
+                    const uint32_t k = k0 + j;
+                    p[j] = *(const __attribute__((address_space(1))) u32x4 *)(tp + (k < sub ? k : sub - 1));
+                }
+            } else {
+                lim = src.template load<PPT>(pts, t, wg, tl.n, p);
+            }
 #pragma unroll
             for (int j = 0; j < PPT; ++j) {
-                const uint32_t k = threadIdx.x * PPT + j;
-                p[j] = *(const __attribute__((address_space(1))) u32x4 *)(tp + (k < lim ? k : lim - 1));
+                uint32_t dbits;
+                const uint32_t k = kSub ? k0 + j : j * wg + threadIdx.x;
+                uint32_t pid = project_wave(v, p[j], k < lim, dbits);
+                u64 key = make_key(dbits, p[j].w);
+                bool w = pid != kEmptyPid;
+                if (adapt && c == 0) {
+                    // the next lane's point of this instruction (PPT points on)
+                    const uint32_t nxt = (uint32_t)__shfl_down((int)pid, 1, 64);
+                    const bool both = w && lane < 63u && nxt != kEmptyPid;
+                    same += __popcll(__ballot(both && pid == nxt));
+                    line += __popcll(__ballot(both && pid != nxt && (pid >> 3) == (nxt >> 3)));
+                }
+                if (REDUCE) w = wave_reduce<u64, true>(pid, key, w);
+                if (EARLYZ && w) w = key < peek_u64(fb + pid);
+                if (w) gmin_u64(fb + pid, key);
             }
-        } else {
-            lim = src.template load<PPT>(pts, t, wg, tl.n, p);
-        }
-#pragma unroll
-        for (int j = 0; j < PPT; ++j) {
-            uint32_t dbits;
-            const uint32_t k = kRuns ? threadIdx.x * PPT + j : j * wg + threadIdx.x;
-            uint32_t pid = project_wave(v, p[j], k < lim, dbits);
-            u64 key = make_key(dbits, p[j].w);
-            bool w = pid != kEmptyPid;
-            if (REDUCE) w = wave_reduce<u64, true>(pid, key, w);
-            if (EARLYZ && w) w = key < peek_u64(fb + pid);
-            if (w) gmin_u64(fb + pid, key);
+            if (adapt && c == 0) runs = same > line;
         }
     }
 }
@@ -726,6 +775,163 @@ __global__ __launch_bounds__(1024) void k_view_pass(const u32x4 *__restrict__ pt
 }
 
 // ---------------------------------------------------------------------------
+// Grouped multi-view passes: every tile of the cloud is loaded once per group
+// of views and rendered into each view of the group in turn, each view with
+// the single-view kernels' tile body (projection, dense-group collapse, LDS
+// deduplication, flush), so a view costs what its single-view pass costs
+// minus the point stream.  Pass 0 renders the closest-point views and the HQ
+// depth passes, pass 1 the HQ colour passes.
+// ---------------------------------------------------------------------------
+
+// One tile into one closest-point view (basic key buffer) or HQ depth buffer.
+// Both use the 64-bit table: an HQ depth goes in the high word (low word 0),
+// so the table's minimum is the smallest depth and the dense-group collapse
+// compares depths as for keys.
+template <int PPT>
+__device__ __forceinline__ void group_tile_closest(Lds<u64> &L, const u32x4 (&p)[PPT], uint32_t lim, const View &v,
+                                                   bool hq, u64 *__restrict__ fb, uint32_t *__restrict__ D,
+                                                   uint32_t &par) {
+    const uint32_t wg = blockDim.x;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        uint32_t dbits;
+        const uint32_t pid = project_wave(v, p[j], (uint32_t)(j * wg + threadIdx.x) < lim, dbits);
+        const u64 val = hq ? (u64)dbits << 32 : make_key(dbits, p[j].w);
+        bool w = dense_collapse<u64>(L, pid, val, pid != kEmptyPid);
+        if (w) {
+            const uint32_t h = L.slot(pid, par);
+            if (h != kNoSlot) {
+                const u64 cur = __hip_atomic_load(L.val + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (val < cur) __hip_atomic_fetch_min(L.val + h, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            } else if (hq) {
+                gmin_u32(D + pid, dbits);
+            } else {
+                gmin_u64(fb + pid, val);
+            }
+        }
+    }
+    lds_barrier();
+    const uint32_t cnt = L.count[par];
+    if (threadIdx.x == 0) L.count[par ^ 1u] = 0;
+    for (uint32_t k = threadIdx.x; k < cnt; k += wg) {
+        const uint32_t h = L.list[k];
+        const uint32_t pid = L.tag[h];
+        const u64 val = L.val[h];
+        L.tag[h] = kEmptyPid;
+        L.val[h] = kEmptyKey;
+        if (hq) gmin_u32(D + pid, (uint32_t)(val >> 32));
+        else gmin_u64(fb + pid, val);
+    }
+    lds_barrier();
+    par ^= 1u;
+}
+
+// One tile into one HQ view's colour sums (the merged two-word colour pass).
+template <int PPT>
+__device__ __forceinline__ void group_tile_color(Lds<Sum2> &L, const u32x4 (&p)[PPT], uint32_t lim, const View &v,
+                                                 const uint32_t *__restrict__ D, u64 *__restrict__ S,
+                                                 uint32_t &par) {
+    const uint32_t wg = blockDim.x;
+    uint32_t pids[PPT], dbs[PPT], dref[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) pids[j] = project_wave(v, p[j], (uint32_t)(j * wg + threadIdx.x) < lim, dbs[j]);
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) dref[j] = D[pids[j] != kEmptyPid ? pids[j] : 0u];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const uint32_t pid = pids[j];
+        bool live = (pid != kEmptyPid) & (__uint_as_float(dbs[j]) <= __uint_as_float(dref[j]) * 1.01f);
+        u64 r = p[j].w & 0xFFu, g = (p[j].w >> 8) & 0xFFu, bl = (p[j].w >> 16) & 0xFFu;
+        u64 rg = (r << 32) | g, ba = (bl << 32) | 1u;
+        wave_group_sums(pid, p[j].w, rg, ba, live);
+        if (!live) continue;
+        const uint32_t h = L.slot(pid, par);
+        if (h == kNoSlot) {
+            gadd_u64(S + 2 * (u64)pid, rg);
+            gadd_u64(S + 2 * (u64)pid + 1, ba);
+            continue;
+        }
+        __hip_atomic_fetch_add(&L.val[h].rg, rg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(&L.val[h].ba, ba, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    lds_barrier();
+    const uint32_t cnt = L.count[par];
+    if (threadIdx.x == 0) L.count[par ^ 1u] = 0;
+    for (uint32_t k = threadIdx.x; k < cnt; k += wg) {
+        const uint32_t h = L.list[k];
+        const uint32_t pid = L.tag[h];
+        const Sum2 sm = L.val[h];
+        L.tag[h] = kEmptyPid;
+        L.val[h].rg = 0;
+        L.val[h].ba = 0;
+        gadd_u64(S + 2 * (u64)pid, sm.rg);
+        gadd_u64(S + 2 * (u64)pid + 1, sm.ba);
+    }
+    lds_barrier();
+    par ^= 1u;
+}
+
+// Items (group g, tile t) in group-major order, tiles in their natural order;
+// workgroup b takes items b, b + grid, ... (the resident workgroups work on one
+// window of one group's point order).  Group g's views are
+// views[index[groups[g].first + k]], k < groups[g].count.
+template <int PPT, int PASS>
+__global__ __launch_bounds__(1024) void k_group_pass(const u32x4 *__restrict__ pts, Tiles tl,
+                                                     const BatchView *__restrict__ views,
+                                                     const uint32_t *__restrict__ index,
+                                                     const BatchGroup *__restrict__ groups,
+                                                     const uint32_t *__restrict__ ngroups, uint32_t hbits) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    using V = typename std::conditional<PASS == 0, u64, Sum2>::type;
+    Lds<V> L(smem, hbits);
+    const uint32_t wg = blockDim.x;
+    const uint32_t HS = 1u << hbits;
+    for (uint32_t s = threadIdx.x; s < HS; s += wg) {
+        L.tag[s] = kEmptyPid;
+        if constexpr (PASS == 0) {
+            L.val[s] = kEmptyKey;
+        } else {
+            L.val[s].rg = 0;
+            L.val[s].ba = 0;
+        }
+    }
+    if (threadIdx.x < 2) L.count[threadIdx.x] = 0;
+    lds_barrier();
+    const uint32_t ng = (uint32_t)__builtin_amdgcn_readfirstlane((int)*ngroups);
+    if (ng == 0 || tl.ntiles == 0) return;
+    // (g, t) of item blockIdx.x, advanced by the grid stride (uniform)
+    uint64_t t = blockIdx.x;
+    uint32_t g = 0;
+    while (t >= tl.ntiles && g < ng) {
+        t -= tl.ntiles;
+        ++g;
+    }
+    uint32_t par = 0;
+    for (; g < ng;) {
+        u32x4 p[PPT];
+        const uint32_t lim = FlatSrc{}.template load<PPT>(pts, t, wg, tl.n, p);
+        const uint32_t first = (uint32_t)__builtin_amdgcn_readfirstlane((int)groups[g].first);
+        const uint32_t count = (uint32_t)__builtin_amdgcn_readfirstlane((int)groups[g].count);
+        for (uint32_t k = 0; k < count; ++k) {
+            const uint32_t vi = (uint32_t)__builtin_amdgcn_readfirstlane((int)index[first + k]);
+            const BatchView *bv = views + vi;
+            const int variant = __builtin_amdgcn_readfirstlane(bv->variant);
+            const View v = uniform_view(&bv->v);
+            if constexpr (PASS == 0) {
+                group_tile_closest<PPT>(L, p, lim, v, variant == PCR_HQ, bv->fb, bv->D, par);
+            } else {
+                if (variant == PCR_HQ) group_tile_color<PPT>(L, p, lim, v, bv->D, bv->S, par);
+            }
+        }
+        t += gridDim.x;
+        while (t >= tl.ntiles && g < ng) {
+            t -= tl.ntiles;
+            ++g;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Resolve (Sec. 3.1 second listing; Sec. 3.5 resolve listing).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_resolve_basic(const u64 *__restrict__ fb,
@@ -827,10 +1033,13 @@ __global__ __launch_bounds__(256) void k_resolve_hq_depth(const uint32_t *__rest
 // ---------------------------------------------------------------------------
 namespace {
 
-Tiles make_tiles(uint64_t n, const Shape &sh, uint32_t &grid) {
+// Tiles of wg * ppt points, or wg * run (run > 0) / wg * kAdaptRun (run = 0,
+// adaptive) for the basic kernel's sub-tiles.
+Tiles make_tiles(uint64_t n, const Shape &sh, uint32_t &grid, uint32_t run = 0, bool basic_runs = false) {
     Tiles tl;
     tl.n = n;
-    uint64_t T = (uint64_t)sh.wg * sh.ppt;
+    tl.run = run;
+    uint64_t T = (uint64_t)sh.wg * (!basic_runs ? sh.ppt : run ? run : kAdaptRun);
     tl.ntiles = (n + T - 1) / T;
     tl.nblocks = tl.ntiles;
     // sh.grid is set by resolve_shape; 0 would mean one workgroup per tile.
@@ -865,7 +1074,8 @@ template <int P>
 struct BasicL {
     static int run(const Launch &L) {
         uint32_t grid;
-        Tiles tl = make_tiles(L.n, L.sh, grid);
+        const bool runs = !(L.flags & (PCR_F_LDS | PCR_F_REDUCE));  // the kernel's lane mapping
+        Tiles tl = make_tiles(L.n, L.sh, grid, runs ? L.sh.run : 0, runs);
         bool ez = L.flags & PCR_F_EARLYZ, rd = L.flags & PCR_F_REDUCE;
         u64 *fb = (u64 *)L.fb;
         if (L.flags & PCR_F_LDS) {
@@ -1101,6 +1311,30 @@ struct ChunkL {
 };
 
 template <int P>
+struct GroupL {
+    static int run(int pass, const u32x4 *pts, uint64_t n, const BatchView *views, const uint32_t *index,
+                   const BatchGroup *groups, const uint32_t *ngroups, const Shape &sh, hipStream_t s) {
+        const uint32_t T = sh.wg * P, hb = lds_hbits(T, sh.slots);
+        const size_t sm0 = lds_bytes(hb, 8), sm1 = lds_bytes(hb, 16);
+        if (sm1 > max_lds()) return fail(PCR_EINVAL, "tile of %u points needs %zu bytes of LDS", T, sm1);
+        if (pass < 0) {
+            int rc = allow_lds((const void *)&k_group_pass<P, 0>, sm0);
+            return rc ? rc : allow_lds((const void *)&k_group_pass<P, 1>, sm1);
+        }
+        uint32_t grid;
+        const Tiles tl = make_tiles(n, sh, grid);
+        if (pass == 0)
+            hipLaunchKernelGGL((k_group_pass<P, 0>), dim3(grid), dim3(sh.wg), sm0, s, pts, tl, views, index, groups,
+                               ngroups, hb);
+        else
+            hipLaunchKernelGGL((k_group_pass<P, 1>), dim3(grid), dim3(sh.wg), sm1, s, pts, tl, views, index, groups,
+                               ngroups, hb);
+        PCR_LAUNCHED();
+        return PCR_OK;
+    }
+};
+
+template <int P>
 struct ViewL {
     static int run(int pass, const u32x4 *pts, uint64_t n, const BatchView *views, const uint32_t *nviews,
                    uint32_t slot, const Shape &sh, hipStream_t s) {
@@ -1130,6 +1364,10 @@ int render_hq_color(const Launch &L, uint32_t w, uint32_t h) { return by_ppt<Col
 int launch_view_pass(int pass, const u32x4 *pts, uint64_t n, const BatchView *views, const uint32_t *nviews,
                      uint32_t slot, const Shape &sh, hipStream_t s) {
     return by_ppt<ViewL>(sh.ppt, pass, pts, n, views, nviews, slot, sh, s);
+}
+int launch_group_pass(int pass, const u32x4 *pts, uint64_t n, const BatchView *views, const uint32_t *index,
+                      const BatchGroup *groups, const uint32_t *ngroups, const Shape &sh, hipStream_t s) {
+    return by_ppt<GroupL>(sh.ppt, pass, pts, n, views, index, groups, ngroups, sh, s);
 }
 
 }  // namespace pcr

@@ -46,7 +46,7 @@ class PcrError(RuntimeError):
 
 class Tune(ctypes.Structure):
     _fields_ = [("ppt", ctypes.c_uint32), ("wg", ctypes.c_uint32), ("grid", ctypes.c_uint32),
-                ("group", ctypes.c_uint32), ("slots", ctypes.c_uint32)]
+                ("group", ctypes.c_uint32), ("slots", ctypes.c_uint32), ("run", ctypes.c_uint32)]
 
 
 class View(ctypes.Structure):
@@ -89,12 +89,19 @@ def _declare(lib):
 
 
 def lib():
-    """The loaded library (raises if it is not built)."""
+    """The loaded library (raises if it is not built).
+
+    torch is imported first: its HIP runtime is then the one the dynamic
+    loader binds libpcr's libamdhip64.so.7 to (same soname), so the library
+    and torch share one runtime, its devices, streams and allocations.
+    Loading libpcr first would put the whole process, torch included, on the
+    system's runtime instead of the one torch was built with."""
     global _lib
     with _lock:
         if _lib is None:
             if not os.path.exists(LIB_PATH):
                 raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2104_07526_amd.build")
+            import torch  # noqa: F401  (see above)
             _lib = _declare(ctypes.CDLL(LIB_PATH))
     return _lib
 
@@ -158,7 +165,7 @@ def _tune(t):
     if isinstance(t, Tune):
         return ctypes.byref(t)
     return ctypes.byref(Tune(int(t.get("ppt", 0)), int(t.get("wg", 0)), int(t.get("grid", 0)),
-                             int(t.get("group", 0)), int(t.get("slots", 0))))
+                             int(t.get("group", 0)), int(t.get("slots", 0)), int(t.get("run", 0))))
 
 
 # ---------------------------------------------------------------------------

@@ -20,12 +20,12 @@ _lock = threading.Lock()
 
 # group 1: each view its own single-view pass inside the plan's graph, with
 # points per thread 1-16 and workgroups of 64-1024 threads (tiles of at most
-# 4096 points, whose LDS tables fit); group > 1: the batched pass (at most 256
-# threads per workgroup), views per point pass 4-32.
+# 4096 points, whose LDS tables fit); group > 1: the grouped passes (each tile
+# loaded once per group of views), views per group 2-32, one-wavefront
+# workgroups with 2-8 points per thread.
 BATCH_CANDIDATES = ([{"ppt": p, "group": 1, "wg": w} for p in (1, 2, 4, 8, 16) for w in (64, 256, 1024)
                      if p * w <= 4096] +
-                    [{"ppt": p, "group": g} for p in (4, 8) for g in (4, 8, 16, 32)] +
-                    [{"ppt": 8, "group": g, "wg": 64} for g in (4, 8, 16, 32)])
+                    [{"ppt": p, "group": g, "wg": 64} for p in (2, 4, 8) for g in (2, 4, 8, 16, 32)])
 RENDER_CANDIDATES = [{"ppt": p, "wg": w, "slots": s} for p in (4, 8, 16) for w in (64, 128, 256, 512)
                      for s in (0, 512, 1024, 2048)]
 

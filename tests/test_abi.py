@@ -153,9 +153,12 @@ def test_batch_argument_checks():
     assert L.pcr_batch_create(ctypes.byref(h), 16, 100, 0, None, None) == pcr.EINVAL
     assert L.pcr_batch_create(ctypes.byref(h), 8, 100, 4, None, None) == pcr.EINVAL
     assert L.pcr_batch_create(ctypes.byref(h), 16, 0, 4, None, None) == pcr.EINVAL
-    tune = pcr.Tune(8, 512, 0, 4, 0)          # batched pass above 256 threads per workgroup
+    tune = pcr.Tune(3, 64, 0, 4, 0)           # points per thread not a power of two
     assert L.pcr_batch_create(ctypes.byref(h), 16, 100, 4, ctypes.byref(tune), None) == pcr.EINVAL
-    assert "workgroup" in L.pcr_last_error().decode()
+    assert "points per thread" in L.pcr_last_error().decode()
+    tune = pcr.Tune(8, 64, 0, 4, 0, 12)       # run not a multiple of ppt
+    assert L.pcr_batch_create(ctypes.byref(h), 16, 100, 4, ctypes.byref(tune), None) == pcr.EINVAL
+    assert "run" in L.pcr_last_error().decode()
     assert L.pcr_batch_launch(None, None, 0, None) == pcr.EINVAL
     assert L.pcr_batch_destroy(None) == pcr.OK
 
@@ -218,3 +221,16 @@ def test_measurement_helpers_check_arguments():
     assert L.pcr_probe_atomics(64, 64, 0, 1, 1, 1, 0, None, None) == pcr.EINVAL   # returning without sink
     assert L.pcr_probe_atomics(64, 64, 0, 0, 0, 1, 0, None, None) == pcr.EINVAL   # no workgroups
 
+
+def test_robust_hq_flag_checks():
+    """PCR_F_HQ_ROBUST belongs to PCR_HQ, excludes PCR_F_HQ_PACKED, and adds
+    one 8-byte fast word per pixel to the framebuffer."""
+    L = pcr.lib()
+    m = (ctypes.c_float * 16)()
+    RB = pcr.HQ | pcr.F_HQ_ROBUST
+    assert L.pcr_fb_bytes(64, 32, RB) == L.pcr_fb_bytes(64, 32, pcr.HQ) + 8 * 64 * 32
+    assert L.pcr_fb_bytes(64, 32, pcr.DEDUP | pcr.F_HQ_ROBUST) == 0
+    assert L.pcr_fb_bytes(64, 32, RB | pcr.F_HQ_PACKED) == 0
+    assert L.pcr_render(None, 0, m, 4, 4, RB | pcr.F_HQ_PACKED, None, None) == pcr.EINVAL
+    assert "pick one" in L.pcr_last_error().decode()
+    assert L.pcr_render(None, 0, m, 4, 4, pcr.BASIC | pcr.F_HQ_ROBUST, None, None) == pcr.EINVAL

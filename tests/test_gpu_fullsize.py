@@ -83,6 +83,18 @@ def test_buildings_300m_hq_1440p(orc):
     cnt = (BA & 0xFFFFFFFF).astype(np.int64)
     assert cnt.max() < 16_843_009          # per-channel sums are exact averages
     assert (cnt > 1).sum() > 100_000       # blending actually happens
+    assert (cnt > 255).sum() > 1000        # the robust form's fast words overflow somewhere
+    log("buildings 300M: HQ bit-exact")
+    # the robust single-atomic form (fast word + fallback words) on the same frame
+    from test_gpu_hq_robust import assert_valid_fast_words, read_robust
+    RB = pcr.HQ | pcr.F_HQ_ROBUST
+    fb = pcr.alloc_fb(W, H, RB)
+    img = frame(msh, m, W, H, RB, fb)
+    gD, gRG, gBA, F = read_robust(fb, W, H)
+    assert np.array_equal(gD, D) and np.array_equal(gRG, RG) and np.array_equal(gBA, BA)
+    assert_valid_fast_words(F)
+    assert np.array_equal(img, ref_img)
+    log("buildings 300M: robust HQ bit-exact")
 
 
 def test_buildings_796m_1080p(orc):

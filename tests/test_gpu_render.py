@@ -14,7 +14,8 @@ BASIC_FORMS = [B, B | EZ, B | RD, B | EZ | RD, B | LDS, B | LDS | EZ, B | LDS | 
                D | pcr.F_PLAIN, B | pcr.F_PLAIN]
 HQ_FORMS = [HQ, HQ | EZ, HQ | RD, HQ | RD | EZ, HQ | LDS, HQ | LDS | EZ, HQ | LDS | RD, HQ | pcr.F_PLAIN]
 SHAPES = [None, {"ppt": 1, "wg": 64}, {"ppt": 8, "wg": 256}, {"ppt": 16, "wg": 64},
-          {"ppt": 2, "wg": 1024}, {"ppt": 4, "wg": 128, "grid": 3}]
+          {"ppt": 2, "wg": 1024}, {"ppt": 4, "wg": 128, "grid": 3}, {"ppt": 4, "run": 128},
+          {"ppt": 2, "run": 6, "grid": 5}]
 
 
 def dense_cloud(seed, n, W=48, H=32):
@@ -173,3 +174,28 @@ def test_oversized_lds_tile_is_rejected():
     with pytest.raises(pcr.PcrError) as e:
         pcr.render(upload(pts), m, W, H, HQ | LDS, fb, tune={"ppt": 16, "wg": 1024})
     assert e.value.code == pcr.EINVAL
+
+
+@pytest.mark.parametrize("shape", [None, {"run": 4}, {"run": 32}, {"run": 128}, {"ppt": 8, "wg": 256},
+                                   {"ppt": 16, "wg": 128}, {"ppt": 1, "run": 0}])
+def test_basic_lane_mappings(orc, shape):
+    """The basic kernel's lane mappings (adaptive default, fixed runs) on a
+    cloud whose first part repeats each position over runs of consecutive
+    points (consecutive points share pixels: the adaptive mapping switches to
+    runs) and whose second part is in random order (it stays interleaved);
+    51,203 points, so tiles and sub-tiles end ragged."""
+    rng = np.random.default_rng(7)
+    W, H = 96, 64
+    m = synth.mvp((0.0, 0.0, 4.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), W, H, fovy=50.0)
+    n1, n2 = 40_000, 11_203
+    p = np.empty(n1 + n2, synth.POINT_DTYPE)
+    base = rng.uniform(-1.6, 1.6, (n1 // 8, 3))
+    xyz = np.repeat(base, 8, axis=0)
+    xyz += rng.normal(0.0, 1e-4, xyz.shape)
+    p["x"][:n1], p["y"][:n1], p["z"][:n1] = xyz.T
+    p["x"][n1:], p["y"][n1:], p["z"][n1:] = rng.uniform(-1.6, 1.6, (n2, 3)).T
+    p["rgba"] = rng.integers(0, 2**32, len(p), dtype=np.uint64).astype(np.uint32)
+    efb, eimg = oracle_frame(orc, p, m, W, H, B)
+    fb, img = render_frame(upload(p), m, W, H, B, tune=shape)
+    assert_same_fb(read_fb(fb, W, H, B), efb, B)
+    assert np.array_equal(img, eimg)
