@@ -241,6 +241,23 @@ int pcr_render_chunks(const pcr_chunk *chunks, uint32_t nchunks, const float mvp
                       uint32_t h, int variant, void *fb, void *scratch, size_t scratch_bytes,
                       const pcr_tune *tune, void *stream);
 
+/* Largest chunk count of pcr_render_chunks_static. */
+#define PCR_STATIC_CHUNKS_MAX (1u << 20)
+
+/* pcr_render_chunks without the scratch argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The chunk offsets live in a device array
+ * owned by the library: 8 * (PCR_STATIC_CHUNKS_MAX + 1) bytes (8 MiB) per GPU,
+ * held from the first call on that GPU until the process ends.  The call
+ * allocates nothing.  Every call on one GPU shares that GPU's array, so calls
+ * whose work overlaps on one GPU (e.g. on two streams) race and give wrong
+ * frames: order them.  The array's old contents never matter (the offsets are
+ * rewritten by each call before use).
+ * Arguments and result as pcr_render_chunks; errors as pcr_render_chunks,
+ * plus PCR_EINVAL for nchunks > PCR_STATIC_CHUNKS_MAX. */
+int pcr_render_chunks_static(const pcr_chunk *chunks, uint32_t nchunks, const float mvp[16], uint32_t w,
+                             uint32_t h, int variant, void *fb, const pcr_tune *tune, void *stream);
+
 /* Resolve pass (Sec. 3.1 second listing, Sec. 3.5 resolve listing).
  *   rgba_out  device, uint32[W*H].
  * Basic/dedup: the colour word of the stored key, 0 where nothing landed.

@@ -1510,6 +1510,52 @@ extern "C" int pcr_render_chunks(const pcr_chunk *chunks, uint32_t nchunks, cons
     return render_chunks_into(chunks, nchunks, mvp, w, h, variant, fb, (uint64_t *)work, tune, (hipStream_t)stream);
 }
 
+// ---------------------------------------------------------------------------
+// Chunked frames without caller scratch: the chunk offsets live in a
+// library-owned device array (one copy per GPU, held until the process ends).
+// ---------------------------------------------------------------------------
+namespace pcr {
+namespace {
+
+static __device__ __align__(256) uint64_t scratch[PCR_STATIC_CHUNKS_MAX + 1];
+
+// Device address of `scratch` on the current device, looked up once per
+// device (in host code the array's name is a host-side stand-in, never a
+// device address).
+int static_scratch(uint64_t **out) {
+    static std::mutex mu;
+    static uint64_t *addr[64] = {nullptr};
+    int dev = 0;
+    PCR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(PCR_EUNSUPPORTED, "device %d: at most 64 devices", dev);
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        PCR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(PCR_EHIP, "hipGetSymbolAddress returned no address");
+        addr[dev] = (uint64_t *)p;
+    }
+    *out = addr[dev];
+    return PCR_OK;
+}
+
+}  // namespace
+}  // namespace pcr
+
+extern "C" int pcr_render_chunks_static(const pcr_chunk *chunks, uint32_t nchunks, const float mvp[16], uint32_t w,
+                                        uint32_t h, int variant, void *fb, const pcr_tune *tune, void *stream) {
+    bool noop;
+    int rc = check_chunks(chunks, nchunks, mvp, w, h, variant, fb, tune, noop);
+    if (rc != PCR_OK || noop) return rc;
+    if (nchunks > PCR_STATIC_CHUNKS_MAX)
+        return fail(PCR_EINVAL, "at most %u chunks without caller scratch (got %u)", (unsigned)PCR_STATIC_CHUNKS_MAX,
+                    nchunks);
+    uint64_t *start = nullptr;
+    rc = static_scratch(&start);
+    if (rc != PCR_OK) return rc;
+    return render_chunks_into(chunks, nchunks, mvp, w, h, variant, fb, start, tune, (hipStream_t)stream);
+}
+
 extern "C" int pcr_resolve(const void *fb, uint32_t w, uint32_t h, int variant, uint32_t *rgba_out,
                            void *stream) {
     int rc = check_image(w, h);

@@ -68,6 +68,7 @@ def _declare(lib):
                                     P, P, P]),
         "pcr_chunks_scratch_bytes": (SZ, [U32]),
         "pcr_render_chunks": (I32, [P, U32, P, U32, U32, I32, P, P, SZ, P, P]),
+        "pcr_render_chunks_static": (I32, [P, U32, P, U32, U32, I32, P, P, P]),
         "pcr_reorder_scratch_bytes": (SZ, [U64, I32, U32]),
         "pcr_reorder": (I32, [P, P, P, U64, I32, U32, U64, P, SZ, P]),
         "pcr_batch_create": (I32, [P, P, U64, U32, P, P]),
@@ -266,6 +267,18 @@ def render_chunks(table, nchunks, mvp, w, h, variant, fb, scratch=None, tune=Non
     _check(lib().pcr_render_chunks(_ptr(table), nchunks, _mvp(mvp), w, h, variant, _ptr(fb), _ptr(scratch),
                                    nbytes, _tune(tune), _stream(stream)))
     return scratch
+
+
+STATIC_CHUNKS_MAX = 1 << 20
+
+
+def render_chunks_static(table, nchunks, mvp, w, h, variant, fb, tune=None, stream=None):
+    """render_chunks without a scratch buffer (pcr_render_chunks_static: the
+    library's own per-GPU array; allocates nothing, calls on one GPU must not
+    overlap)."""
+    _fb_fits(fb, w, h, variant)
+    _check(lib().pcr_render_chunks_static(_ptr(table), nchunks, _mvp(mvp), w, h, variant, _ptr(fb), _tune(tune),
+                                          _stream(stream)))
 
 
 def depth_coeffs(near, far, reverse=False):

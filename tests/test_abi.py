@@ -222,6 +222,19 @@ def test_measurement_helpers_check_arguments():
     assert L.pcr_probe_atomics(64, 64, 0, 0, 0, 1, 0, None, None) == pcr.EINVAL   # no workgroups
 
 
+def test_static_chunks_refuse_too_many_chunks():
+    """pcr_render_chunks_static refuses more chunks than its array holds, and
+    its other checks match pcr_render_chunks (host only, nothing enqueued)."""
+    L = pcr.lib()
+    m = (ctypes.c_float * 16)()
+    assert L.pcr_render_chunks_static(16, pcr.STATIC_CHUNKS_MAX + 1, m, 4, 4, pcr.DEDUP, 16, None, None) == pcr.EINVAL
+    assert "chunks" in L.pcr_last_error().decode()
+    assert L.pcr_render_chunks_static(16, 3, m, 4, 4, pcr.DEDUP | pcr.F_EARLYZ, 16, None, None) == pcr.EUNSUPPORTED
+    assert L.pcr_render_chunks_static(16, 3, m, 4, 4, pcr.DEDUP, None, None, None) == pcr.EINVAL
+    assert L.pcr_render_chunks_static(None, 3, m, 4, 4, pcr.DEDUP, 16, None, None) == pcr.EINVAL
+    assert L.pcr_render_chunks_static(None, 0, m, 4, 4, pcr.DEDUP, 16, None, None) == pcr.OK
+
+
 def test_robust_hq_flag_checks():
     """PCR_F_HQ_ROBUST belongs to PCR_HQ, excludes PCR_F_HQ_PACKED, and adds
     one 8-byte fast word per pixel to the framebuffer."""
