@@ -161,6 +161,8 @@ class GpuBackend:
         plan, stream = self.plans[cloud][pi], self.streams[si]
         for img in images:
             img.record_stream(stream)
+        # a marker range per batch for rocprofv3's marker trace (roctx)
+        self.torch.cuda.nvtx.range_push(f"serve cloud {cloud}: {len(reqs)} views, stream {si}")
         try:
             if len(reqs) < self.min_plan_views:
                 # Too few views to share the point stream: the single-view
@@ -182,6 +184,8 @@ class GpuBackend:
             # memory to other requests.
             stream.synchronize()
             raise
+        finally:
+            self.torch.cuda.nvtx.range_pop()
         ev = self.torch.cuda.Event()
         ev.record(stream)
         self.stream_busy[si] = ev
