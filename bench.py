@@ -164,11 +164,12 @@ def cpu_baseline(pts, m, W, H, frames_per_step, what, target_s=12.0):
     orc.resolve_basic(fb, W, H)
     per_pt = (time.perf_counter() - t) / probe
     n = int(min(len(pts), max(probe, target_s / max(per_pt, 1e-12))))
-    reps = max(frames_per_step, int(round(target_s / max(per_pt * n, 1e-9))))
+    reps = 0
     t = time.perf_counter()
-    for _ in range(reps):
+    while reps < frames_per_step or time.perf_counter() - t < target_s:
         fb = orc.render_basic(pts[:n], m, W, H)
         orc.resolve_basic(fb, W, H)
+        reps += 1
     dt = time.perf_counter() - t
     scope = "the whole cloud" if n == len(pts) else f"the first {n} points"
     return {"value": round(n * reps / dt / 1e9, 4), "unit": "Gpts/s", "cores": 1, "kind": "oracle",

@@ -144,20 +144,26 @@ enum {
 
 /* Launch shape for the render kernels.  Zero fields take the defaults
  * (measured on MI355X), all with 64-thread (one-wavefront) workgroups that
- * step over the tiles in their natural order: basic 4 consecutive points per
- * thread and 64 workgroups per compute unit; deduplicating 4 and HQ 8 points
- * per thread, 256 LDS slots and 512 workgroups per compute unit.
+ * step over the tiles in their natural order: basic 4 points per thread per
+ * step, adaptive lane mapping over 2,048-point sub-tiles and 64 workgroups
+ * per compute unit; deduplicating 4 and HQ 8 points per thread, 256 LDS slots
+ * and 512 workgroups per compute unit.
  *   ppt    points per thread (1, 2, 4, 8 or 16)
  *   wg     workgroup size (64, 128, 256, 512 or 1024)
  *   grid   workgroups per launch; each takes tiles g, g + grid, ... (0 = the
  *          default above)
- *   group  views per point pass in a batch (0 = all that fit the cache budget;
- *          1 = every view its own pass with the single-view kernels)
+ *   group  views per group of a batch's grouped passes (0 = up to 16 whose
+ *          framebuffers fit the cache budget; 1 = every view its own pass with
+ *          the single-view kernels)
  *   slots  LDS hash-table slots per workgroup of the deduplicating kernels,
  *          rounded up to a power of two in [256, 32768] (0 = half a tile)
  *   run    basic kernel (PCR_BASIC without flags): consecutive points per lane,
- *          a multiple of ppt up to 4096, taken ppt at a time (0 = ppt); one
- *          atomic instruction then covers points `run` apart */
+ *          a multiple of ppt up to 4096, taken ppt at a time, so that one
+ *          atomic instruction covers points `run` apart; 0 = adaptive: per
+ *          wavefront and sub-tile of 2,048 points, lanes on neighbouring
+ *          points while they fall on distinct pixels of shared cache lines,
+ *          runs of 28 points (for 4 per step) while neighbouring points
+ *          share pixels.  Any value gives the same framebuffer. */
 typedef struct pcr_tune {
     uint32_t ppt;
     uint32_t wg;
@@ -322,10 +328,10 @@ typedef struct pcr_view {
 } pcr_view;
 
 /* A batch plan renders up to `capacity` views of one resident point buffer per
- * launch: the framebuffers are cleared, every view's points are rendered in
- * persistent kernels that load each point once per group of views (or, with
- * tune->group == 1, by one single-view render pass per view slot), and every
- * view is resolved.  The launch is a single hipGraph replay.  Each view's
+ * launch: the framebuffers are cleared, the views are rendered by grouped
+ * passes that load each tile of points once per group of views and render it
+ * into each view of the group in turn (or, with tune->group == 1, by one
+ * single-view render pass per view slot), and every view is resolved.  The launch is a single hipGraph replay.  Each view's
  * image is bit-identical to pcr_fb_clear + pcr_render + pcr_resolve of that
  * view alone.  The plan allocates its device view table and graph at
  * creation; pcr_batch_launch allocates nothing.  A plan is not thread-safe;
