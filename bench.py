@@ -947,6 +947,8 @@ def leg_techniques(args):
         "early-z": pcr.BASIC | pcr.F_EARLYZ,
         "reduce": pcr.BASIC | pcr.F_REDUCE,
         "reduce&early-z": pcr.BASIC | pcr.F_REDUCE | pcr.F_EARLYZ,
+        "reduce(wave)": pcr.BASIC | pcr.F_REDUCE_WAVE,
+        "reduce(pairs)": pcr.BASIC | pcr.F_REDUCE_PAIR,
         "dedup(LDS)": pcr.BASIC | pcr.F_LDS,
         "dedup": pcr.DEDUP,
         "dedup&early-z": pcr.DEDUP | pcr.F_LDS | pcr.F_REDUCE | pcr.F_EARLYZ,

@@ -77,9 +77,10 @@ enum {
 enum { PCR_BASIC = 0, PCR_DEDUP = 1, PCR_HQ = 2 };
 
 /* Flag bits OR-ed into `variant`.  They select the update path only: every
- * combination yields bit-identical framebuffers.  With none of
- * EARLYZ/REDUCE/LDS/PLAIN the variant's default path is used: PCR_BASIC = one
- * global atomic per point; PCR_DEDUP and PCR_HQ = the tuned merging path.
+ * combination yields bit-identical framebuffers.  With none of EARLYZ,
+ * REDUCE (or its two steps), LDS and PLAIN the variant's default path is
+ * used: PCR_BASIC = one global atomic per point; PCR_DEDUP and PCR_HQ = the
+ * tuned merging path.
  *   PCR_F_EARLYZ  read the stored value first, skip the atomic when it is not
  *                 larger (Sec. 3.2; safe because values only decrease)
  *   PCR_F_REDUCE  merge same-pixel updates inside a wavefront before the
@@ -88,6 +89,10 @@ enum { PCR_BASIC = 0, PCR_DEDUP = 1, PCR_HQ = 2 };
  *                 two leaders with 24 or more lanes each); without PCR_F_LDS, neighbouring lane pairs
  *                 then merge as well (Sec. 3.3).  For PCR_HQ it applies to
  *                 the depth pass.
+ *   PCR_F_REDUCE_WAVE / PCR_F_REDUCE_PAIR  one of PCR_F_REDUCE's two steps
+ *                 alone: the leader groups, or the neighbouring pairs (the
+ *                 latter only without PCR_F_LDS, else PCR_EINVAL).  Both
+ *                 bits = PCR_F_REDUCE.
  *   PCR_F_LDS     merge all equal pixels of a workgroup's tile in an LDS hash
  *                 table before the atomics (Sec. 3.4's deduplication)
  *   PCR_F_PLAIN   none of the above (for PCR_HQ: one global atomic per sum
@@ -132,7 +137,9 @@ enum {
     PCR_F_HQ_DEPTH = 1 << 12,
     PCR_F_HQ_COLOR = 1 << 13,
     PCR_F_HQ_PACKED = 1 << 14,
-    PCR_F_HQ_ROBUST = 1 << 15
+    PCR_F_HQ_ROBUST = 1 << 15,
+    PCR_F_REDUCE_WAVE = 1 << 16,
+    PCR_F_REDUCE_PAIR = 1 << 17
 };
 
 /* Vertex orders (Sec. 4, Sec. 5). */
@@ -152,9 +159,9 @@ enum {
  *   wg     workgroup size (64, 128, 256, 512 or 1024)
  *   grid   workgroups per launch; each takes tiles g, g + grid, ... (0 = the
  *          default above)
- *   group  views per group of a batch's grouped passes (0 = up to 16 whose
- *          framebuffers fit the cache budget; 1 = every view its own pass with
- *          the single-view kernels)
+ *   group  views per group of a batch's grouped passes (0 = 16, at most 32;
+ *          a group also closes at 2 GiB of framebuffers; 1 = every view its
+ *          own pass with the single-view kernels)
  *   slots  LDS hash-table slots per workgroup of the deduplicating kernels,
  *          rounded up to a power of two in [256, 32768] (0 = half a tile)
  *   run    basic kernel (PCR_BASIC without flags): consecutive points per lane,

@@ -37,8 +37,10 @@ int check_variant(int variant) {
     if (fam != PCR_BASIC && fam != PCR_DEDUP && fam != PCR_HQ)
         return fail(PCR_EINVAL, "unknown variant %d", fam);
     uint32_t allowed = fam == PCR_HQ ? (kFlagMask | kHqPassMask | PCR_F_HQ_PACKED | PCR_F_HQ_ROBUST) : kFlagMask;
-    if ((flags & PCR_F_PLAIN) && (flags & (PCR_F_EARLYZ | PCR_F_REDUCE | PCR_F_LDS)))
+    if ((flags & PCR_F_PLAIN) && (flags & (PCR_F_EARLYZ | kReduceMask | PCR_F_LDS)))
         return fail(PCR_EINVAL, "PCR_F_PLAIN excludes the other path flags");
+    if ((flags & PCR_F_REDUCE_PAIR) && (flags & PCR_F_LDS))
+        return fail(PCR_EINVAL, "PCR_F_REDUCE_PAIR applies to the paths without PCR_F_LDS");
     if ((flags & PCR_F_HQ_PACKED) && (flags & PCR_F_HQ_ROBUST))
         return fail(PCR_EINVAL, "PCR_F_HQ_PACKED and PCR_F_HQ_ROBUST are two layouts of the sums: pick one");
     if (flags & ~allowed) return fail(PCR_EINVAL, "flag bits 0x%x do not apply to variant %d", flags & ~allowed, fam);

@@ -10,9 +10,8 @@
 // over (group, tile) items in group-major order, load the tile's points once
 // and render them into every view of the group in turn with the single-view
 // kernels' tile body, so the point stream is read once per group instead of
-// once per view.  Views are grouped so that a group's framebuffers fit the
-// cache budget, which keeps the atomics of a pass inside a cache-resident
-// working set.  In the per-view form (tune group 1) every view slot runs the
+// once per view.  A group holds up to tune group views (16 by default) and
+// at most 2 GiB of framebuffers.  In the per-view form (tune group 1) every view slot runs the
 // single-view passes instead, reading its view from the device table; slots a
 // launch does not use are disabled in the graph.  Every update is an integer
 // min or sum, so each view is bit-identical to rendering it alone.
@@ -27,7 +26,11 @@
 namespace pcr {
 namespace {
 
-constexpr uint64_t kGroupBudget = 160ull << 20;  // framebuffer bytes per group
+// Framebuffer bytes per group.  Fewer, larger groups read the point stream
+// fewer times; a group's framebuffers need not stay cache resident (the
+// atomics execute at the memory side), so only the view count limits a group
+// of ordinary images.
+constexpr uint64_t kGroupBudget = 2048ull << 20;
 constexpr uint32_t kMaxGroup = 32;                // views per group
 constexpr uint32_t kPidMask = (1u << 27) - 1u;    // largest pixel count of a batched view
 

@@ -22,7 +22,14 @@ typedef unsigned long long u64;
 
 constexpr u64 kEmptyKey = ~0ull;
 constexpr uint32_t kEmptyPid = 0xFFFFFFFFu;
-constexpr uint32_t kFlagMask = PCR_F_EARLYZ | PCR_F_REDUCE | PCR_F_LDS | PCR_F_PLAIN;
+constexpr uint32_t kReduceMask = PCR_F_REDUCE | PCR_F_REDUCE_WAVE | PCR_F_REDUCE_PAIR;
+constexpr uint32_t kFlagMask = PCR_F_EARLYZ | kReduceMask | PCR_F_LDS | PCR_F_PLAIN;
+
+// Wavefront reductions of a flag set: bit 0 leader groups, bit 1 neighbouring
+// pairs (PCR_F_REDUCE = both).
+inline int reduce_mode(uint32_t flags) {
+    return ((flags & (PCR_F_REDUCE | PCR_F_REDUCE_WAVE)) ? 1 : 0) | ((flags & (PCR_F_REDUCE | PCR_F_REDUCE_PAIR)) ? 2 : 0);
+}
 constexpr uint32_t kHqPassMask = PCR_F_HQ_DEPTH | PCR_F_HQ_COLOR;
 
 // Camera and viewport of one view, passed by value as a kernel argument (the

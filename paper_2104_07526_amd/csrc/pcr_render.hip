@@ -102,14 +102,15 @@ __device__ __forceinline__ V lane_pair(V x) {
     }
 }
 
-template <typename V, bool PAIRS>
+// RED: bit 0 = leader groups (all lanes equal), bit 1 = neighbouring pairs.
+template <typename V, int RED>
 __device__ __forceinline__ bool wave_reduce(uint32_t pid, V val, bool live) {
     // Leader groups: the lanes sharing the first remaining live lane's pixel
     // keep only their minimum (with every live lane in one group this is the
     // all-lanes-equal case of Sec. 3.3).  Up to two groups of at least 24
     // lanes; a wavefront spread over several pixels leaves after one ballot.
     const uint32_t lane = __lane_id();
-    uint64_t act = __ballot(live);
+    uint64_t act = (RED & 1) ? __ballot(live) : 0ull;
 #pragma unroll 1
     for (int it = 0; it < 2 && act; ++it) {
         uint32_t leader = (uint32_t)__builtin_ctzll(act);
@@ -121,7 +122,7 @@ __device__ __forceinline__ bool wave_reduce(uint32_t pid, V val, bool live) {
         if (in) live = depth_of(val) == md;  // the group's minimum is among these lanes
         act &= ~m;
     }
-    if (!PAIRS) return live;
+    if (!(RED & 2)) return live;
     // Neighbouring lane pairs merge (Sec. 3.3, pairs).
     uint32_t ppid = lane_pair(live ? pid : kEmptyPid);
     V pval = lane_pair(val);
@@ -418,12 +419,13 @@ struct ChunkSrc {
 // case and best summed over them.)
 constexpr uint32_t kAdaptRun = 32;
 
-template <int PPT, bool EARLYZ, bool REDUCE, class Src>
+// RED: the wavefront reductions (bit 0 leader groups, bit 1 pairs; 0 none).
+template <int PPT, bool EARLYZ, int RED, class Src>
 __global__ __launch_bounds__(1024) void k_basic(const u32x4 *__restrict__ pts, Tiles tl, View v,
                                                 u64 *__restrict__ fb, Src src) {
     const uint32_t wg = blockDim.x;
     if constexpr (Src::chunked) src.setup(tl, wg * PPT);
-    constexpr bool kSub = !REDUCE && !Src::chunked;
+    constexpr bool kSub = RED == 0 && !Src::chunked;
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     const bool adapt = kSub && tl.run == 0;
     const uint32_t run = !kSub ? PPT : (adapt ? kAdaptRun : tl.run);
@@ -476,7 +478,7 @@ __global__ __launch_bounds__(1024) void k_basic(const u32x4 *__restrict__ pts, T
                     same += __popcll(__ballot(both && pid == nxt));
                     line += __popcll(__ballot(both && pid != nxt && (pid >> 3) == (nxt >> 3)));
                 }
-                if (REDUCE) w = wave_reduce<u64, true>(pid, key, w);
+                if (RED) w = wave_reduce<u64, RED>(pid, key, w);
                 if (EARLYZ && w) w = key < peek_u64(fb + pid);
                 if (w) gmin_u64(fb + pid, key);
             }
@@ -565,8 +567,8 @@ __global__ __launch_bounds__(1024) void k_dedup(const u32x4 *__restrict__ pts, T
 }
 
 // HQ depth pass without LDS (Sec. 3.5: a 32-bit atomicMin of the depth),
-// optionally with the wavefront reduction of Sec. 3.3 on the depth bits.
-template <int PPT, bool EARLYZ, bool REDUCE>
+// optionally with the wavefront reductions of Sec. 3.3 on the depth bits.
+template <int PPT, bool EARLYZ, int RED>
 __global__ __launch_bounds__(1024) void k_hq_depth(const u32x4 *__restrict__ pts, Tiles tl, View v,
                                                    uint32_t *__restrict__ D) {
     const uint32_t wg = blockDim.x;
@@ -583,7 +585,7 @@ __global__ __launch_bounds__(1024) void k_hq_depth(const u32x4 *__restrict__ pts
             uint32_t dbits;
             uint32_t pid = project_wave(v, p[j], (uint32_t)(j * wg + threadIdx.x) < lim, dbits);
             bool w = pid != kEmptyPid;
-            if (REDUCE) w = wave_reduce<uint32_t, true>(pid, dbits, w);
+            if (RED) w = wave_reduce<uint32_t, RED>(pid, dbits, w);
             if (EARLYZ && w) w = dbits < peek_u32(D + pid);
             if (w) gmin_u32(D + pid, dbits);
         }
@@ -1074,9 +1076,10 @@ template <int P>
 struct BasicL {
     static int run(const Launch &L) {
         uint32_t grid;
-        const bool runs = !(L.flags & (PCR_F_LDS | PCR_F_REDUCE));  // the kernel's lane mapping
+        const int red = reduce_mode(L.flags);
+        const bool runs = !(L.flags & PCR_F_LDS) && red == 0;  // the kernel's lane mapping
         Tiles tl = make_tiles(L.n, L.sh, grid, runs ? L.sh.run : 0, runs);
-        bool ez = L.flags & PCR_F_EARLYZ, rd = L.flags & PCR_F_REDUCE;
+        const bool ez = L.flags & PCR_F_EARLYZ, rd = red != 0;
         u64 *fb = (u64 *)L.fb;
         if (L.flags & PCR_F_LDS) {
             uint32_t T = L.sh.wg * P, hb = lds_hbits(T, L.sh.slots);
@@ -1097,10 +1100,16 @@ struct BasicL {
         } else {
 #define PCR_BB(E, R) \
     hipLaunchKernelGGL((k_basic<P, E, R, FlatSrc>), dim3(grid), dim3(L.sh.wg), 0, L.s, L.pts, tl, L.v, fb, FlatSrc{})
-            if (ez && rd) PCR_BB(true, true);
-            else if (ez) PCR_BB(true, false);
-            else if (rd) PCR_BB(false, true);
-            else PCR_BB(false, false);
+#define PCR_BR(E)                \
+    do {                         \
+        if (red == 3) PCR_BB(E, 3); \
+        else if (red == 2) PCR_BB(E, 2); \
+        else if (red == 1) PCR_BB(E, 1); \
+        else PCR_BB(E, 0);       \
+    } while (0)
+            if (ez) PCR_BR(true);
+            else PCR_BR(false);
+#undef PCR_BR
 #undef PCR_BB
         }
         PCR_LAUNCHED();
@@ -1113,7 +1122,8 @@ struct DepthL {
     static int run(const Launch &L) {
         uint32_t grid;
         Tiles tl = make_tiles(L.n, L.sh, grid);
-        bool ez = L.flags & PCR_F_EARLYZ, rd = L.flags & PCR_F_REDUCE;
+        const int red = reduce_mode(L.flags);
+        const bool ez = L.flags & PCR_F_EARLYZ, rd = red != 0;
         uint32_t *D = (uint32_t *)L.fb;
         if (L.flags & PCR_F_LDS) {
             uint32_t T = L.sh.wg * P, hb = lds_hbits(T, L.sh.slots);
@@ -1133,10 +1143,16 @@ struct DepthL {
 #undef PCR_DD
         } else {
 #define PCR_HD(E, R) hipLaunchKernelGGL((k_hq_depth<P, E, R>), dim3(grid), dim3(L.sh.wg), 0, L.s, L.pts, tl, L.v, D)
-            if (ez && rd) PCR_HD(true, true);
-            else if (ez) PCR_HD(true, false);
-            else if (rd) PCR_HD(false, true);
-            else PCR_HD(false, false);
+#define PCR_HR(E)                \
+    do {                         \
+        if (red == 3) PCR_HD(E, 3); \
+        else if (red == 2) PCR_HD(E, 2); \
+        else if (red == 1) PCR_HD(E, 1); \
+        else PCR_HD(E, 0);       \
+    } while (0)
+            if (ez) PCR_HR(true);
+            else PCR_HR(false);
+#undef PCR_HR
 #undef PCR_HD
         }
         PCR_LAUNCHED();
@@ -1273,8 +1289,8 @@ struct ChunkL {
         const uint32_t wg = C.sh.wg, T = wg * P, hb = lds_hbits(T, C.sh.slots);
         const Tiles tl{};
         if (C.fam == PCR_BASIC) {
-            const void *fn = (const void *)&k_basic<P, false, false, ChunkSrc>;
-            hipLaunchKernelGGL((k_basic<P, false, false, ChunkSrc>), dim3(persistent_grid(fn, wg, 0, C.sh.grid)),
+            const void *fn = (const void *)&k_basic<P, false, 0, ChunkSrc>;
+            hipLaunchKernelGGL((k_basic<P, false, 0, ChunkSrc>), dim3(persistent_grid(fn, wg, 0, C.sh.grid)),
                                dim3(wg), 0, C.s, nullptr, tl, C.v, (u64 *)C.fb, C.src);
             PCR_LAUNCHED();
             return PCR_OK;

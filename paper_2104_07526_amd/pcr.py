@@ -29,6 +29,8 @@ F_HQ_DEPTH = 1 << 12
 F_HQ_COLOR = 1 << 13
 F_HQ_PACKED = 1 << 14
 F_HQ_ROBUST = 1 << 15
+F_REDUCE_WAVE = 1 << 16
+F_REDUCE_PAIR = 1 << 17
 ORDER_MORTON, ORDER_MORTON_SHUFFLE, ORDER_SHUFFLE = 0, 1, 2
 DEPTH_LINEAR, DEPTH_HYPERBOLIC = 0, 1
 

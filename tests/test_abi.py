@@ -60,6 +60,10 @@ def test_fb_bytes():
     (pcr.BASIC | (1 << 20), "flag bits"),
     (pcr.DEDUP | pcr.F_HQ_COLOR, "flag bits"),
     (pcr.DEDUP | pcr.F_PLAIN | pcr.F_LDS, "PLAIN"),
+    (pcr.BASIC | pcr.F_PLAIN | pcr.F_REDUCE_WAVE, "PLAIN"),
+    (pcr.HQ | pcr.F_PLAIN | pcr.F_REDUCE_PAIR, "PLAIN"),
+    (pcr.BASIC | pcr.F_LDS | pcr.F_REDUCE_PAIR, "PAIR"),
+    (pcr.HQ | pcr.F_LDS | pcr.F_REDUCE_PAIR, "PAIR"),
 ])
 def test_render_rejects_bad_variants(variant, msg):
     m = (ctypes.c_float * 16)()
@@ -123,6 +127,8 @@ def test_chunk_argument_checks():
         assert L.pcr_render_chunks(16, 3, m, 4, 4, v, 16, 256, 256, None, None) in (pcr.EUNSUPPORTED, pcr.EINVAL)
     assert L.pcr_render_chunks(16, 3, m, 4, 4, pcr.BASIC | pcr.F_EARLYZ, 16, 256, 256, None, None) == \
         pcr.EUNSUPPORTED
+    for v in (pcr.BASIC | pcr.F_REDUCE_WAVE, pcr.HQ | pcr.F_REDUCE_PAIR):
+        assert L.pcr_render_chunks(16, 3, m, 4, 4, v, 16, 256, 256, None, None) == pcr.EUNSUPPORTED
 
 
 def test_render_batch_argument_checks():

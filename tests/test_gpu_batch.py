@@ -102,16 +102,23 @@ def test_empty_unused_and_capacity(orc, scene):
 
 
 def test_large_views_group_split(orc):
-    """Views whose framebuffers exceed one group's cache budget are split over
-    several point passes; 1080p and 4K views of a 2M-point terrain."""
+    """Views whose framebuffers exceed one group's 2 GiB are split over
+    several point passes: three 8K HQ views (663 MB each) and an 8K basic
+    view (265 MB) pass the limit at the fourth HQ view; plus 1080p and 720p
+    views, over a 2M-point terrain."""
     import torch
     pts = synth.terrain(2_000_000, seed=2)
     d = upload(pts)
-    views = [(synth.terrain_oblique(1920, 1080), 1920, 1080, pcr.DEDUP),
-             (synth.terrain_oblique(3840, 2160), 3840, 2160, pcr.HQ),
-             (synth.terrain_closeup(3840, 2160), 3840, 2160, pcr.BASIC),
+    W8, H8 = 7680, 4320
+    views = [(synth.terrain_oblique(W8, H8), W8, H8, pcr.HQ),
+             (synth.terrain_overview(W8, H8), W8, H8, pcr.HQ),
+             (synth.terrain_closeup(W8, H8), W8, H8, pcr.BASIC),
+             (synth.terrain_oblique(1920, 1080), 1920, 1080, pcr.DEDUP),
+             (synth.terrain_closeup(W8, H8), W8, H8, pcr.HQ),
              (synth.terrain_overview(1280, 720), 1280, 720, pcr.HQ)]
-    plan = pcr.BatchPlan(d, capacity=4)
+    fbb = [pcr.fb_bytes(W, H, var) for _, W, H, var in views]
+    assert sum(fbb[:4]) <= 2 << 30 < sum(fbb[:5])
+    plan = pcr.BatchPlan(d, capacity=6)
     bufs = run_batch(plan, views)
     for (m, W, H, var), (fb, img) in zip(views, bufs):
         _, eimg = oracle_frame(orc, pts, m, W, H, var)

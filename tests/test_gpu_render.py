@@ -10,9 +10,11 @@ pytestmark = pytest.mark.gpu
 
 B, D, HQ = pcr.BASIC, pcr.DEDUP, pcr.HQ
 EZ, RD, LDS = pcr.F_EARLYZ, pcr.F_REDUCE, pcr.F_LDS
-BASIC_FORMS = [B, B | EZ, B | RD, B | EZ | RD, B | LDS, B | LDS | EZ, B | LDS | RD, B | LDS | EZ | RD, D,
-               D | pcr.F_PLAIN, B | pcr.F_PLAIN]
-HQ_FORMS = [HQ, HQ | EZ, HQ | RD, HQ | RD | EZ, HQ | LDS, HQ | LDS | EZ, HQ | LDS | RD, HQ | pcr.F_PLAIN]
+WV, PR = pcr.F_REDUCE_WAVE, pcr.F_REDUCE_PAIR
+BASIC_FORMS = [B, B | EZ, B | RD, B | EZ | RD, B | WV, B | PR, B | EZ | WV, B | EZ | PR, B | LDS, B | LDS | EZ,
+               B | LDS | RD, B | LDS | WV, B | LDS | EZ | RD, D, D | pcr.F_PLAIN, B | pcr.F_PLAIN]
+HQ_FORMS = [HQ, HQ | EZ, HQ | RD, HQ | RD | EZ, HQ | WV, HQ | PR | EZ, HQ | LDS, HQ | LDS | EZ, HQ | LDS | RD,
+            HQ | LDS | WV, HQ | pcr.F_PLAIN]
 SHAPES = [None, {"ppt": 1, "wg": 64}, {"ppt": 8, "wg": 256}, {"ppt": 16, "wg": 64},
           {"ppt": 2, "wg": 1024}, {"ppt": 4, "wg": 128, "grid": 3}, {"ppt": 4, "run": 128},
           {"ppt": 2, "run": 6, "grid": 5}]
