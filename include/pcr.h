@@ -279,6 +279,20 @@ int pcr_render_chunks_static(const pcr_chunk *chunks, uint32_t nchunks, const fl
 int pcr_resolve(const void *fb, uint32_t w, uint32_t h, int variant, uint32_t *rgba_out,
                 void *stream);
 
+/* The framebuffer's words in one linear layout, whatever the sum layout, for
+ * tests and tools (the raw output the resolve of Sec. 3.1 and Sec. 3.5 reads).
+ *   raw_out  device, 8-byte aligned:
+ *            PCR_BASIC / PCR_DEDUP: uint64[W*H], the keys as stored;
+ *            PCR_HQ: uint64[3*W*H], three planes: the depth bits (zero-
+ *            extended; 0xFFFFFFFF where nothing landed), R << 32 | G sums,
+ *            B << 32 | count.  With PCR_F_HQ_ROBUST the fast and fallback
+ *            words are combined (the words equal PCR_HQ's); with
+ *            PCR_F_HQ_PACKED the packed word's fields as stored (18-bit
+ *            colour sums, 10-bit count).
+ * Errors: as pcr_resolve. */
+int pcr_resolve_raw(const void *fb, uint32_t w, uint32_t h, int variant, unsigned long long *raw_out,
+                    void *stream);
+
 /* Depth output modes of pcr_resolve_depth. */
 enum { PCR_DEPTH_LINEAR = 0, PCR_DEPTH_HYPERBOLIC = 1 };
 

@@ -1030,6 +1030,38 @@ __global__ __launch_bounds__(256) void k_resolve_hq_depth(const uint32_t *__rest
     }
 }
 
+// Raw framebuffer words in one linear layout.  Closest-point frames: the keys
+// as stored.  HQ: three planes of npix words, the depth bits (zero-extended),
+// R << 32 | G and B << 32 | count; a robust frame's fast and fallback words
+// are combined into these two, a packed word's four fields are spread over
+// them (as stored, so a wrapped count stays wrapped).
+__global__ __launch_bounds__(256) void k_raw_basic(const u64 *__restrict__ fb, u64 *__restrict__ out,
+                                                   uint64_t npix) {
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npix; i += stride) out[i] = fb[i];
+}
+
+template <int SUMS>
+__global__ __launch_bounds__(256) void k_raw_hq(const uint32_t *__restrict__ D, const u64 *__restrict__ S,
+                                                u64 *__restrict__ out, uint64_t npix) {
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npix; i += stride) {
+        u64 rg, ba;
+        if constexpr (SUMS == kPacked) {
+            const u64 w = S[i];
+            rg = (w >> 46) << 32 | ((w >> 28) & 0x3FFFFull);
+            ba = ((w >> 10) & 0x3FFFFull) << 32 | (w & 0x3FFull);
+        } else {
+            const u32x4 s = SUMS == kRobust ? robust_words(S, S + 2 * npix, i) : ((const u32x4 *)S)[i];
+            rg = (u64)s.y << 32 | s.x;
+            ba = (u64)s.w << 32 | s.z;
+        }
+        out[i] = D[i];
+        out[npix + i] = rg;
+        out[2 * npix + i] = ba;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
@@ -1594,6 +1626,35 @@ extern "C" int pcr_resolve(const void *fb, uint32_t w, uint32_t h, int variant, 
             hipLaunchKernelGGL(k_resolve_hq<kTwoWord>, dim3(grid), dim3(256), 0, s, S, rgba_out, px);
     } else {
         hipLaunchKernelGGL(k_resolve_basic, dim3(grid), dim3(256), 0, s, (const u64 *)fb, rgba_out, px);
+    }
+    PCR_LAUNCHED();
+    return PCR_OK;
+}
+
+extern "C" int pcr_resolve_raw(const void *fb, uint32_t w, uint32_t h, int variant, unsigned long long *raw_out,
+                               void *stream) {
+    int rc = check_image(w, h);
+    if (rc == PCR_OK) rc = check_variant(variant);
+    if (rc != PCR_OK) return rc;
+    if (!fb || ((uintptr_t)fb & 15)) return fail(PCR_EINVAL, "framebuffer must be a 16-byte aligned device pointer");
+    if (!raw_out || ((uintptr_t)raw_out & 7)) return fail(PCR_EINVAL, "raw_out must be an 8-byte aligned device pointer");
+    const uint64_t px = (uint64_t)w * h;
+    const uint64_t want = (px + 255) / 256;
+    const uint32_t grid = (uint32_t)(want > 16384 ? 16384 : want);
+    hipStream_t s = (hipStream_t)stream;
+    u64 *out = (u64 *)raw_out;
+    if ((variant & 0xFF) == PCR_HQ) {
+        const uint32_t *D = (const uint32_t *)fb;
+        const u64 *S = (const u64 *)((const char *)fb + hq_depth_bytes(w, h));
+        const int sums = sums_layout((uint32_t)variant);
+        if (sums == kPacked)
+            hipLaunchKernelGGL(k_raw_hq<kPacked>, dim3(grid), dim3(256), 0, s, D, S, out, px);
+        else if (sums == kRobust)
+            hipLaunchKernelGGL(k_raw_hq<kRobust>, dim3(grid), dim3(256), 0, s, D, S, out, px);
+        else
+            hipLaunchKernelGGL(k_raw_hq<kTwoWord>, dim3(grid), dim3(256), 0, s, D, S, out, px);
+    } else {
+        hipLaunchKernelGGL(k_raw_basic, dim3(grid), dim3(256), 0, s, (const u64 *)fb, out, px);
     }
     PCR_LAUNCHED();
     return PCR_OK;

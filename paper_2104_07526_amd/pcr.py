@@ -66,6 +66,7 @@ def _declare(lib):
         "pcr_render": (I32, [P, U64, P, U32, U32, I32, P, P]),
         "pcr_render_ex": (I32, [P, U64, P, U32, U32, I32, P, P, P]),
         "pcr_resolve": (I32, [P, U32, U32, I32, P, P]),
+        "pcr_resolve_raw": (I32, [P, U32, U32, I32, P, P]),
         "pcr_resolve_depth": (I32, [P, U32, U32, I32, I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                     P, P, P]),
         "pcr_chunks_scratch_bytes": (SZ, [U32]),
@@ -243,6 +244,19 @@ def resolve(fb, w, h, variant, out=None, stream=None):
     _fb_fits(fb, w, h, variant)
     _fits(out, 4 * w * h, "image")
     _check(lib().pcr_resolve(_ptr(fb), w, h, variant, _ptr(out), _stream(stream)))
+    return out
+
+
+def resolve_raw(fb, w, h, variant, out=None, stream=None):
+    """The framebuffer's words in one linear layout (int64 tensor): the keys
+    [w*h], or for HQ three planes [3*w*h] of depth bits, R<<32|G, B<<32|count."""
+    import torch
+    planes = 3 if (variant & 0xFF) == HQ else 1
+    if out is None:
+        out = torch.empty(planes * w * h, dtype=torch.int64, device=fb.device)
+    _fb_fits(fb, w, h, variant)
+    _fits(out, 8 * planes * w * h, "raw output")
+    _check(lib().pcr_resolve_raw(_ptr(fb), w, h, variant, _ptr(out), _stream(stream)))
     return out
 
 

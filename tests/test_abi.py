@@ -25,7 +25,7 @@ def test_header_declares_the_boundary():
     names = declared()
     for n in ("pcr_fb_bytes", "pcr_fb_clear", "pcr_render", "pcr_render_ex", "pcr_resolve", "pcr_resolve_depth",
               "pcr_reorder_scratch_bytes", "pcr_reorder", "pcr_batch_create", "pcr_batch_launch",
-              "pcr_batch_destroy", "pcr_last_error", "pcr_version"):
+              "pcr_batch_destroy", "pcr_last_error", "pcr_version", "pcr_resolve_raw"):
         assert n in names
 
 
@@ -106,6 +106,11 @@ def test_render_rejects_bad_pointers_and_sizes():
     assert L.pcr_resolve_depth(8, 4, 4, 0, 1, 0.0, 0.0, 0.0, None, 16, None) == pcr.EINVAL     # fb align
     assert L.pcr_resolve_depth(16, 4, 4, 7, 1, 0.0, 0.0, 0.0, None, 16, None) == pcr.EINVAL    # variant
     assert L.pcr_fb_clear(None, 4, 4, 0, None) == pcr.EINVAL
+    assert L.pcr_resolve_raw(16, 4, 4, 0, None, None) == pcr.EINVAL                     # no raw_out
+    assert L.pcr_resolve_raw(16, 4, 4, pcr.HQ, 12, None) == pcr.EINVAL                  # raw_out align
+    assert L.pcr_resolve_raw(8, 4, 4, 0, 16, None) == pcr.EINVAL                        # fb align
+    assert L.pcr_resolve_raw(16, 0, 4, 0, 16, None) == pcr.EINVAL                       # size
+    assert L.pcr_resolve_raw(16, 4, 4, pcr.HQ | pcr.F_HQ_PACKED | pcr.F_HQ_ROBUST, 16, None) == pcr.EINVAL
 
 
 def test_chunk_argument_checks():
