@@ -346,13 +346,21 @@ struct ChunkSrc {
     const u32x4 *cur_pts;
     uint64_t cur_n;
 
-    // Last c with start[c] <= t (start[0] = 0 <= t < start[nchunks]).
+    // Last c with start[c] <= t (start[0] = 0 <= t < start[nchunks]): a
+    // 64-way search, each lane testing one of 64 evenly spaced entries of
+    // [lo, hi) per level (start is non-decreasing, so the lanes that pass
+    // form a prefix); three levels cover 2^18 chunks.  Called by whole
+    // wavefronts with a uniform t.
     __device__ __forceinline__ uint32_t find(uint64_t t) const {
         uint32_t lo = 0, hi = nchunks;
         while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) / 2;
-            if (start[mid] <= t) lo = mid;
-            else hi = mid;
+            const uint32_t step = (hi - lo + 63) / 64;
+            const uint32_t idx = lo + (__lane_id() + 1) * step;
+            const bool le = idx < hi && start[idx] <= t;
+            const uint32_t k = (uint32_t)__popcll(__ballot(le));
+            const uint32_t nhi = lo + (k + 1) * step;
+            lo += k * step;
+            hi = nhi < hi ? nhi : hi;
         }
         return lo;
     }
@@ -1240,20 +1248,33 @@ __device__ __forceinline__ uint64_t shfl_up64(uint64_t x, uint32_t d) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// One workgroup of 1024 threads takes 8192 chunks per step, 8 consecutive
+// chunks per thread: the 8 records are loaded together, summed in the thread,
+// and the thread totals scanned across the workgroup; tiles hold 2^tshift
+// points (a power of two).
+constexpr uint32_t kStartsPer = 8;
+
 __global__ __launch_bounds__(1024) void k_chunk_starts(const pcr_chunk *__restrict__ chunks, uint32_t nchunks,
-                                                       uint32_t T, uint64_t *__restrict__ start) {
+                                                       uint32_t tshift, uint64_t *__restrict__ start) {
     __shared__ uint64_t wtot[16];
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint64_t T = 1ull << tshift;
     uint64_t carry = 0;
-    for (uint32_t base = 0; base < nchunks; base += blockDim.x) {
-        const uint32_t i = base + threadIdx.x;
-        uint64_t c = 0;
-        if (i < nchunks) {
-            const pcr_chunk ch = chunks[i];
-            const bool ok = ch.pts != nullptr && ((uintptr_t)ch.pts & 15u) == 0 && ch.n <= PCR_CHUNK_MAX_POINTS;
-            c = ok ? (ch.n + T - 1) / T : 0;  // tiles of the chunk
+    for (uint32_t base = 0; base < nchunks; base += blockDim.x * kStartsPer) {
+        const uint32_t i0 = base + threadIdx.x * kStartsPer;
+        uint64_t c[kStartsPer];
+        uint64_t sum = 0;
+#pragma unroll
+        for (uint32_t r = 0; r < kStartsPer; ++r) {
+            c[r] = 0;
+            if (i0 + r < nchunks) {
+                const pcr_chunk ch = chunks[i0 + r];
+                const bool ok = ch.pts != nullptr && ((uintptr_t)ch.pts & 15u) == 0 && ch.n <= PCR_CHUNK_MAX_POINTS;
+                c[r] = ok ? (ch.n + T - 1) >> tshift : 0;  // tiles of the chunk
+            }
+            sum += c[r];
         }
-        uint64_t x = c;  // inclusive scan over the wavefront
+        uint64_t x = sum;  // inclusive scan of the thread totals over the wavefront
         for (uint32_t d = 1; d < 64; d <<= 1) {
             const uint64_t y = shfl_up64(x, d);
             if (lane >= d) x += y;
@@ -1265,7 +1286,12 @@ __global__ __launch_bounds__(1024) void k_chunk_starts(const pcr_chunk *__restri
             if (k < wid) before += wtot[k];
             total += wtot[k];
         }
-        if (i < nchunks) start[i] = before + x - c;
+        uint64_t run = before + x - sum;
+#pragma unroll
+        for (uint32_t r = 0; r < kStartsPer; ++r) {
+            if (i0 + r < nchunks) start[i0 + r] = run;
+            run += c[r];
+        }
         carry = total;
         __syncthreads();
     }
@@ -1507,7 +1533,9 @@ int render_chunks_into(const pcr_chunk *chunks, uint32_t nchunks, const float mv
     Shape sh;
     int rc = resolve_shape(tune, fam, sh);
     if (rc != PCR_OK) return rc;
-    hipLaunchKernelGGL(k_chunk_starts, dim3(1), dim3(1024), 0, s, chunks, nchunks, sh.wg * sh.ppt, start);
+    // wg and ppt are powers of two (checked by resolve_shape), so is a tile.
+    const uint32_t tshift = (uint32_t)__builtin_ctz(sh.wg * sh.ppt);
+    hipLaunchKernelGGL(k_chunk_starts, dim3(1), dim3(1024), 0, s, chunks, nchunks, tshift, start);
     PCR_LAUNCHED();
     uint32_t pass = flags & kHqPassMask;
     if (pass == 0) pass = kHqPassMask;

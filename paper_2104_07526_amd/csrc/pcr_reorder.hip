@@ -35,18 +35,31 @@ __global__ __launch_bounds__(64) void k_bbox_init(uint32_t *bb) {
     else if (threadIdx.x == 8) bb[8] = 0u;                    // rank of the partial batch
 }
 
+// Each step a thread has kBboxLoads points in flight (consecutive threads on
+// consecutive points in each of them).
+constexpr uint32_t kBboxLoads = 8;
+
+__device__ __forceinline__ void bbox_add(const u32x4 &p, uint32_t (&lo)[3], uint32_t (&hi)[3]) {
+    const uint32_t k[3] = {ord(__uint_as_float(p.x)), ord(__uint_as_float(p.y)), ord(__uint_as_float(p.z))};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = k[a] < lo[a] ? k[a] : lo[a];
+        hi[a] = k[a] > hi[a] ? k[a] : hi[a];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_bbox(const u32x4 *__restrict__ pts, uint64_t n, uint32_t *bb) {
     uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, hi[3] = {0u, 0u, 0u};
-    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        u32x4 p = load_point(pts + i);
-        uint32_t k[3] = {ord(__uint_as_float(p.x)), ord(__uint_as_float(p.y)), ord(__uint_as_float(p.z))};
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + (kBboxLoads - 1) * stride < n; i += kBboxLoads * stride) {
+        u32x4 p[kBboxLoads];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = k[a] < lo[a] ? k[a] : lo[a];
-            hi[a] = k[a] > hi[a] ? k[a] : hi[a];
-        }
+        for (uint32_t r = 0; r < kBboxLoads; ++r) p[r] = load_point(pts + i + r * stride);
+#pragma unroll
+        for (uint32_t r = 0; r < kBboxLoads; ++r) bbox_add(p[r], lo, hi);
     }
+    for (; i < n; i += stride) bbox_add(load_point(pts + i), lo, hi);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
 #pragma unroll
@@ -159,11 +172,17 @@ __global__ __launch_bounds__(kSortWg) void k_sort_hist(const uint64_t *__restric
     __syncthreads();
     const uint32_t wave = threadIdx.x / 64, lane = __lane_id();
     const uint64_t base = (uint64_t)blockIdx.x * kSortTile + wave * (64 * kSortIpt);
+    uint64_t k[kSortIpt];  // all loads issued before the first use
+#pragma unroll
     for (uint32_t r = 0; r < kSortIpt; ++r) {
-        uint64_t i = base + r * 64 + lane;
-        bool live = i < n;
-        uint32_t d = live ? (uint32_t)(keys[i] >> shift) & 0xFFu : 0u;
-        uint64_t pm = peers(d, live);
+        const uint64_t i = base + r * 64 + lane;
+        k[r] = i < n ? keys[i] : 0ull;
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < kSortIpt; ++r) {
+        const bool live = base + r * 64 + lane < n;
+        const uint32_t d = (uint32_t)(k[r] >> shift) & 0xFFu;
+        const uint64_t pm = peers(d, live);
         if (live && (pm & lanes_below()) == 0) atomicAdd(&cnt[d], (uint32_t)__popcll(pm));
     }
     __syncthreads();
