@@ -240,14 +240,17 @@ size_t pcr_chunks_scratch_bytes(uint32_t nchunks);
  *              misaligned pointer, or more than PCR_CHUNK_MAX_POINTS points,
  *              is skipped (contributes nothing); n == 0 is an empty chunk.
  *   nchunks    at most 2^24; 0 is a no-op.
- *   scratch    device, at least pcr_chunks_scratch_bytes(nchunks) bytes,
- *              256-byte aligned; overwritten (chunk start offsets).
+ *   scratch    device, at least pcr_chunks_scratch_bytes(nchunks) bytes
+ *              (8 bytes per chunk plus 512 KiB), 256-byte aligned;
+ *              overwritten (chunk start offsets, each workgroup's first
+ *              chunk).
  *   variant    PCR_BASIC, PCR_DEDUP or PCR_HQ; PCR_HQ optionally with one
  *              PCR_F_HQ_DEPTH / PCR_F_HQ_COLOR pass bit and PCR_F_HQ_PACKED;
  *              the other flag bits give PCR_EUNSUPPORTED.
- *   tune       as pcr_render_ex (may be NULL); grid 0 = as many workgroups as
- *              are resident at once.  Tiles of wg*ppt points never span two
- *              chunks (the last tile of a chunk is partial).
+ *   tune       as pcr_render_ex (may be NULL); the grid is at most 2^17
+ *              workgroups (larger values are clamped), each taking one
+ *              contiguous range of tiles.  Tiles of wg*ppt points never span
+ *              two chunks (the last tile of a chunk is partial).
  * Errors: PCR_EINVAL (as pcr_render, plus NULL chunks with nchunks > 0,
  * nchunks > 2^24), PCR_ENOMEM (scratch too small). */
 int pcr_render_chunks(const pcr_chunk *chunks, uint32_t nchunks, const float mvp[16], uint32_t w,
@@ -259,13 +262,14 @@ int pcr_render_chunks(const pcr_chunk *chunks, uint32_t nchunks, const float mvp
 
 /* pcr_render_chunks without the scratch argument, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
- * harnesses that forbid hipMalloc).  The chunk offsets live in a device array
- * owned by the library: 8 * (PCR_STATIC_CHUNKS_MAX + 1) bytes (8 MiB) per GPU,
- * held from the first call on that GPU until the process ends.  The call
+ * harnesses that forbid hipMalloc).  The scratch lives in a device array
+ * owned by the library, pcr_chunks_scratch_bytes(PCR_STATIC_CHUNKS_MAX) bytes
+ * (8.5 MiB) per GPU, held from the first call on that GPU until the process
+ * ends.  The call
  * allocates nothing.  Every call on one GPU shares that GPU's array, so calls
  * whose work overlaps on one GPU (e.g. on two streams) race and give wrong
- * frames: order them.  The array's old contents never matter (the offsets are
- * rewritten by each call before use).
+ * frames: order them.  The array's old contents never matter (each call
+ * rewrites what it reads before use).
  * Arguments and result as pcr_render_chunks; errors as pcr_render_chunks,
  * plus PCR_EINVAL for nchunks > PCR_STATIC_CHUNKS_MAX. */
 int pcr_render_chunks_static(const pcr_chunk *chunks, uint32_t nchunks, const float mvp[16], uint32_t w,

@@ -4,9 +4,7 @@
 // Data layout in HBM: points are a 16-byte array streamed once per geometry
 // pass with non-temporal 16-byte loads (one point per lane, 1 KiB per wave per
 // load); framebuffers are small (7-166 MB) and stay in L2 / Infinity Cache.
-#include <map>
 #include <mutex>
-#include <tuple>
 #include <type_traits>
 
 #include "pcr_internal.h"
@@ -336,6 +334,7 @@ struct ChunkSrc {
     static constexpr bool chunked = true;
     const pcr_chunk *chunks;
     const uint64_t *start;
+    const uint32_t *wgc;  // chunk of each workgroup's first tile (k_chunk_wg)
     uint32_t nchunks;
     // Per workgroup (set up in the kernel): the contiguous tile range
     // [t_next, t_end), the chunk `cur` holding tile t_next, and that chunk's
@@ -346,24 +345,6 @@ struct ChunkSrc {
     const u32x4 *cur_pts;
     uint64_t cur_n;
 
-    // Last c with start[c] <= t (start[0] = 0 <= t < start[nchunks]): a
-    // 64-way search, each lane testing one of 64 evenly spaced entries of
-    // [lo, hi) per level (start is non-decreasing, so the lanes that pass
-    // form a prefix); three levels cover 2^18 chunks.  Called by whole
-    // wavefronts with a uniform t.
-    __device__ __forceinline__ uint32_t find(uint64_t t) const {
-        uint32_t lo = 0, hi = nchunks;
-        while (hi - lo > 1) {
-            const uint32_t step = (hi - lo + 63) / 64;
-            const uint32_t idx = lo + (__lane_id() + 1) * step;
-            const bool le = idx < hi && start[idx] <= t;
-            const uint32_t k = (uint32_t)__popcll(__ballot(le));
-            const uint32_t nhi = lo + (k + 1) * step;
-            lo += k * step;
-            hi = nhi < hi ? nhi : hi;
-        }
-        return lo;
-    }
     __device__ __forceinline__ void enter(uint32_t c) {
         cur = c;
         cur_first = start[c];
@@ -383,7 +364,7 @@ struct ChunkSrc {
         t_next = lo < tl.ntiles ? lo : tl.ntiles;
         t_end = t_next + per_wg < tl.ntiles ? t_next + per_wg : tl.ntiles;
         tl.nblocks = blockIdx.x + (t_end - t_next) * gridDim.x;  // this workgroup's loop count
-        if (t_next < t_end) enter(find(t_next));
+        if (t_next < t_end) enter(wgc[blockIdx.x]);
     }
     __device__ __forceinline__ bool tile(const Tiles &, uint64_t, uint64_t &t) {
         t = t_next++;
@@ -1298,24 +1279,31 @@ __global__ __launch_bounds__(1024) void k_chunk_starts(const pcr_chunk *__restri
     if (threadIdx.x == 0) start[nchunks] = carry;
 }
 
-// Workgroups resident at once (a multiple of 8), unless the caller fixed it.
-// The occupancy query is made once per device, kernel and launch shape.
-uint32_t persistent_grid(const void *fn, uint32_t wg, size_t sm, uint32_t want) {
-    if (want) return want;
-    static std::mutex mu;
-    static std::map<std::tuple<int, const void *, uint32_t, size_t>, uint32_t> cache;
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    const auto key = std::make_tuple(dev, fn, wg, sm);
-    std::lock_guard<std::mutex> g(mu);
-    auto it = cache.find(key);
-    if (it != cache.end()) return it->second;
-    int per = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, (int)wg, sm) != hipSuccess || per < 1) per = 1;
-    uint32_t grid = (uint32_t)per * (uint32_t)device_cus() / 8u * 8u;
-    if (grid < 8u) grid = 8u;
-    cache.emplace(key, grid);
-    return grid;
+// Workgroups of a chunked launch: at most kChunkGridMax (the scratch holds
+// one word per workgroup).
+constexpr uint32_t kChunkGridMax = 1u << 17;
+
+// Chunk of the first tile of every workgroup of a chunked launch of `grid`
+// workgroups (workgroup b takes tiles [b * per, (b + 1) * per), per =
+// ceil(tiles / grid), as ChunkSrc::setup): the last c with start[c] <= b * per,
+// by binary search, one thread per workgroup, so that a render workgroup
+// starts with one dependent load instead of a search.
+__global__ __launch_bounds__(256) void k_chunk_wg(const uint64_t *__restrict__ start, uint32_t nchunks,
+                                                  uint32_t grid, uint32_t *__restrict__ wgc) {
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= grid) return;
+    const uint64_t ntiles = start[nchunks];
+    const uint64_t per = (ntiles + grid - 1) / grid;
+    const uint64_t t = (uint64_t)b * per;
+    uint32_t lo = 0, hi = nchunks;
+    if (t < ntiles) {
+        while (hi - lo > 1) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            if (start[mid] <= t) lo = mid;
+            else hi = mid;
+        }
+    }
+    wgc[b] = lo;
 }
 
 struct ChunkLaunch {
@@ -1338,8 +1326,8 @@ struct ChunkL {
         if (int rc = allow_lds(fn, sm)) return rc;
         const uint32_t *D = (const uint32_t *)C.fb;
         u64 *S = (u64 *)((char *)C.fb + hq_depth_bytes(C.w, C.h));
-        hipLaunchKernelGGL((k_hq_color<P, true, ChunkSrc, SUMS>), dim3(persistent_grid(fn, C.sh.wg, sm, C.sh.grid)),
-                           dim3(C.sh.wg), sm, C.s, nullptr, tl, C.v, D, S, hb, C.src);
+        hipLaunchKernelGGL((k_hq_color<P, true, ChunkSrc, SUMS>), dim3(C.sh.grid), dim3(C.sh.wg), sm,
+                           C.s, nullptr, tl, C.v, D, S, hb, C.src);
         PCR_LAUNCHED();
         return PCR_OK;
     }
@@ -1347,9 +1335,8 @@ struct ChunkL {
         const uint32_t wg = C.sh.wg, T = wg * P, hb = lds_hbits(T, C.sh.slots);
         const Tiles tl{};
         if (C.fam == PCR_BASIC) {
-            const void *fn = (const void *)&k_basic<P, false, 0, ChunkSrc>;
-            hipLaunchKernelGGL((k_basic<P, false, 0, ChunkSrc>), dim3(persistent_grid(fn, wg, 0, C.sh.grid)),
-                               dim3(wg), 0, C.s, nullptr, tl, C.v, (u64 *)C.fb, C.src);
+            hipLaunchKernelGGL((k_basic<P, false, 0, ChunkSrc>), dim3(C.sh.grid), dim3(wg), 0, C.s, nullptr, tl, C.v,
+                               (u64 *)C.fb, C.src);
             PCR_LAUNCHED();
             return PCR_OK;
         }
@@ -1358,8 +1345,8 @@ struct ChunkL {
             if (sm > max_lds()) return fail(PCR_EINVAL, "tile of %u points needs %zu bytes of LDS", T, sm);
             const void *fn = (const void *)&k_dedup<u64, P, false, true, ChunkSrc>;
             if (int rc = allow_lds(fn, sm)) return rc;
-            hipLaunchKernelGGL((k_dedup<u64, P, false, true, ChunkSrc>), dim3(persistent_grid(fn, wg, sm, C.sh.grid)),
-                               dim3(wg), sm, C.s, nullptr, tl, C.v, (u64 *)C.fb, hb, C.src);
+            hipLaunchKernelGGL((k_dedup<u64, P, false, true, ChunkSrc>), dim3(C.sh.grid), dim3(wg), sm, C.s, nullptr,
+                               tl, C.v, (u64 *)C.fb, hb, C.src);
             PCR_LAUNCHED();
             return PCR_OK;
         }
@@ -1368,9 +1355,8 @@ struct ChunkL {
             if (sm > max_lds()) return fail(PCR_EINVAL, "tile of %u points needs %zu bytes of LDS", T, sm);
             const void *fn = (const void *)&k_dedup<uint32_t, P, false, true, ChunkSrc>;
             if (int rc = allow_lds(fn, sm)) return rc;
-            hipLaunchKernelGGL((k_dedup<uint32_t, P, false, true, ChunkSrc>),
-                               dim3(persistent_grid(fn, wg, sm, C.sh.grid)), dim3(wg), sm, C.s, nullptr, tl, C.v,
-                               (uint32_t *)C.fb, hb, C.src);
+            hipLaunchKernelGGL((k_dedup<uint32_t, P, false, true, ChunkSrc>), dim3(C.sh.grid), dim3(wg), sm, C.s,
+                               nullptr, tl, C.v, (uint32_t *)C.fb, hb, C.src);
             PCR_LAUNCHED();
         }
         if (C.pass & PCR_F_HQ_COLOR) {
@@ -1516,30 +1502,38 @@ extern "C" int pcr_render(const pcr_point *pts, uint64_t n, const float mvp[16],
     return pcr_render_ex(pts, n, mvp, w, h, variant, fb, nullptr, stream);
 }
 
+// Chunk scratch: the chunks' tile offsets (nchunks + 1 words, padded to 256
+// bytes), then the first chunk of each workgroup (kChunkGridMax words).
+static size_t chunk_starts_bytes(uint32_t nchunks) { return ((size_t)8 * (nchunks + 1) + 255) / 256 * 256; }
+
 extern "C" size_t pcr_chunks_scratch_bytes(uint32_t nchunks) {
     if (nchunks == 0 || nchunks > (1u << 24)) return 0;
-    return ((size_t)8 * (nchunks + 1) + 255) / 256 * 256;
+    return chunk_starts_bytes(nchunks) + (size_t)4 * kChunkGridMax;
 }
 
 namespace pcr {
 namespace {
 
-// Renders a chunk table with `start` (device, nchunks + 1 words) as the
-// chunks' tile offsets.  Arguments other than `start` are checked here.
+// Renders a chunk table with `work` (device, pcr_chunks_scratch_bytes bytes)
+// as its scratch.  Arguments other than `work` are checked here.
 int render_chunks_into(const pcr_chunk *chunks, uint32_t nchunks, const float mvp[16], uint32_t w, uint32_t h,
-                       int variant, void *fb, uint64_t *start, const pcr_tune *tune, hipStream_t s) {
+                       int variant, void *fb, void *work, const pcr_tune *tune, hipStream_t s) {
     const int fam = variant & 0xFF;
     const uint32_t flags = (uint32_t)variant & ~0xFFu;
     Shape sh;
     int rc = resolve_shape(tune, fam, sh);
     if (rc != PCR_OK) return rc;
+    if (sh.grid > kChunkGridMax) sh.grid = kChunkGridMax;
+    uint64_t *start = (uint64_t *)work;
+    uint32_t *wgc = (uint32_t *)((char *)work + chunk_starts_bytes(nchunks));
     // wg and ppt are powers of two (checked by resolve_shape), so is a tile.
     const uint32_t tshift = (uint32_t)__builtin_ctz(sh.wg * sh.ppt);
     hipLaunchKernelGGL(k_chunk_starts, dim3(1), dim3(1024), 0, s, chunks, nchunks, tshift, start);
+    hipLaunchKernelGGL(k_chunk_wg, dim3((sh.grid + 255) / 256), dim3(256), 0, s, start, nchunks, sh.grid, wgc);
     PCR_LAUNCHED();
     uint32_t pass = flags & kHqPassMask;
     if (pass == 0) pass = kHqPassMask;
-    ChunkLaunch C{ChunkSrc{chunks, start, nchunks}, make_view(mvp, w, h), fb, fam, pass,
+    ChunkLaunch C{ChunkSrc{chunks, start, wgc, nchunks}, make_view(mvp, w, h), fb, fam, pass,
                   sums_layout(flags), sh, w, h, s};
     return by_ppt<ChunkL>(sh.ppt, C);
 }
@@ -1583,7 +1577,7 @@ extern "C" int pcr_render_chunks(const pcr_chunk *chunks, uint32_t nchunks, cons
     const size_t need = pcr_chunks_scratch_bytes(nchunks);
     if (work_bytes < need)
         return fail(PCR_ENOMEM, "scratch holds %zu bytes, %u chunks need %zu", work_bytes, nchunks, need);
-    return render_chunks_into(chunks, nchunks, mvp, w, h, variant, fb, (uint64_t *)work, tune, (hipStream_t)stream);
+    return render_chunks_into(chunks, nchunks, mvp, w, h, variant, fb, work, tune, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -1593,7 +1587,9 @@ extern "C" int pcr_render_chunks(const pcr_chunk *chunks, uint32_t nchunks, cons
 namespace pcr {
 namespace {
 
-static __device__ __align__(256) uint64_t scratch[PCR_STATIC_CHUNKS_MAX + 1];
+// Sized as pcr_chunks_scratch_bytes(PCR_STATIC_CHUNKS_MAX), in 8-byte words.
+constexpr size_t kStaticWords = ((size_t)8 * (PCR_STATIC_CHUNKS_MAX + 1) + 255) / 256 * 32 + kChunkGridMax / 2;
+static __device__ __align__(256) uint64_t scratch[kStaticWords];
 
 // Device address of `scratch` on the current device, looked up once per
 // device (in host code the array's name is a host-side stand-in, never a
@@ -1626,10 +1622,10 @@ extern "C" int pcr_render_chunks_static(const pcr_chunk *chunks, uint32_t nchunk
     if (nchunks > PCR_STATIC_CHUNKS_MAX)
         return fail(PCR_EINVAL, "at most %u chunks without caller scratch (got %u)", (unsigned)PCR_STATIC_CHUNKS_MAX,
                     nchunks);
-    uint64_t *start = nullptr;
-    rc = static_scratch(&start);
+    uint64_t *work = nullptr;
+    rc = static_scratch(&work);
     if (rc != PCR_OK) return rc;
-    return render_chunks_into(chunks, nchunks, mvp, w, h, variant, fb, start, tune, (hipStream_t)stream);
+    return render_chunks_into(chunks, nchunks, mvp, w, h, variant, fb, work, tune, (hipStream_t)stream);
 }
 
 extern "C" int pcr_resolve(const void *fb, uint32_t w, uint32_t h, int variant, uint32_t *rgba_out,

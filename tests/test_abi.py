@@ -118,8 +118,8 @@ def test_chunk_argument_checks():
     m = (ctypes.c_float * 16)()
     assert L.pcr_chunks_scratch_bytes(0) == 0
     assert L.pcr_chunks_scratch_bytes((1 << 24) + 1) == 0
-    assert L.pcr_chunks_scratch_bytes(1) == 256
-    assert L.pcr_chunks_scratch_bytes(100) == 1024
+    assert L.pcr_chunks_scratch_bytes(1) == 256 + 4 * (1 << 17)       # offsets, then one word per workgroup
+    assert L.pcr_chunks_scratch_bytes(100) == 1024 + 4 * (1 << 17)
     # nothing to draw: accepted without touching any pointer
     assert L.pcr_render_chunks(None, 0, m, 4, 4, pcr.DEDUP, 16, None, 0, None, None) == pcr.OK
     assert L.pcr_render_chunks(None, 3, m, 4, 4, pcr.DEDUP, 16, 256, 256, None, None) == pcr.EINVAL
