@@ -607,22 +607,25 @@ __device__ __forceinline__ u64 packed_sums(u64 rg, u64 ba) {
 // plus c stays within 255 the new word is the old one plus the update;
 // otherwise the word is swapped to zero and the update goes to the fallback
 // words together with the old word's sums (the transfer of the paper's
-// overflowing thread).  A swap that fails (another update landed first)
+// overflowing thread).  The first swap assumes a cleared word (right for a
+// pixel's first update; otherwise it fails and returns the current word at
+// the atomic unit, a fresher guess than a separate load); a swap that fails
 // retries with the value it returned; after kRobustTries failures, and for
 // updates of more than 255 points, the update goes to the fallback words
-// alone.  The fast word only ever changes by a successful swap from a value
+// alone (few retries keep hot pixels from queueing swaps that mostly fail).
+// The fast word only ever changes by a successful swap from a value
 // its thread knows exactly, so every completed update is counted exactly once
 // in F or in the fallback, whatever number of updates is in flight: the sums
 // are exact with no bound on concurrency (the paper's single add needs fewer
 // than 65,280 adds to land between the overflow and the reset).  The resolve
 // adds F's fields to the fallback words.
-constexpr int kRobustTries = 4;
+constexpr int kRobustTries = 2;
 
 __device__ __forceinline__ void robust_add(u64 *__restrict__ F, u64 *__restrict__ S, uint32_t pid, u64 rg, u64 ba) {
     const uint32_t c = (uint32_t)ba;
     if (c <= 255u) {
         const u64 v = (rg >> 32) << 48 | (rg & 0xFFFFull) << 32 | (ba >> 32) << 16 | c;
-        u64 exp = peek_u64(F + pid);
+        u64 exp = 0;
 #pragma unroll 1
         for (int a = 0; a < kRobustTries; ++a) {
             const bool fits = ((uint32_t)exp & 0xFFFFu) + c <= 255u;
