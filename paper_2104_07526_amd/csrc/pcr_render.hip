@@ -109,8 +109,9 @@ __device__ __forceinline__ bool wave_reduce(uint32_t pid, V val, bool live) {
     // lanes; a wavefront spread over several pixels leaves after one ballot.
     const uint32_t lane = __lane_id();
     uint64_t act = (RED & 1) ? __ballot(live) : 0ull;
+    // A group is a subset of act: with fewer than 24 lanes left none can form.
 #pragma unroll 1
-    for (int it = 0; it < 2 && act; ++it) {
+    for (int it = 0; it < 2 && __popcll(act) >= 24; ++it) {
         uint32_t leader = (uint32_t)__builtin_ctzll(act);
         uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pid, leader);
         uint64_t m = __ballot(live && pid == p0);
@@ -140,7 +141,7 @@ __device__ __forceinline__ void wave_group_sums(uint32_t pid, uint32_t rgba, u64
     const uint32_t lane = __lane_id();
     uint64_t act = __ballot(live);
 #pragma unroll 1
-    for (int it = 0; it < 2 && act; ++it) {
+    for (int it = 0; it < 2 && __popcll(act) >= 4; ++it) {  // a group is a subset of act
         uint32_t leader = (uint32_t)__builtin_ctzll(act);
         uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pid, leader);
         uint64_t m = __ballot(live && pid == p0);
@@ -205,12 +206,15 @@ struct Lds {
     // tile with parity `par`), or kNoSlot when kMaxProbe slots in a row are
     // taken by other pixels -- the caller then updates the framebuffer
     // directly, which is always correct because min and + commute.
+    // The home slot is tested before the probing loop: most updates find
+    // their pixel there, and the loop's divergent control flow is then
+    // skipped by the whole wavefront.
     __device__ __forceinline__ uint32_t slot(uint32_t pid, uint32_t par) {
         uint32_t h = home(pid);
+        uint32_t t = __hip_atomic_load(tag + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (t == pid) return h;
 #pragma unroll 1
-        for (uint32_t probe = 0; probe < kMaxProbe; ++probe) {
-            uint32_t t = __hip_atomic_load(tag + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (t == pid) return h;
+        for (uint32_t probe = 1;; ++probe) {
             if (t == kEmptyPid) {
                 uint32_t old = atomicCAS(tag + h, kEmptyPid, pid);
                 if (old == kEmptyPid) {
@@ -219,9 +223,11 @@ struct Lds {
                 }
                 if (old == pid) return h;
             }
+            if (probe == kMaxProbe) return kNoSlot;
             h = (h + 1u) & mask;
+            t = __hip_atomic_load(tag + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (t == pid) return h;
         }
-        return kNoSlot;
     }
 };
 
@@ -244,7 +250,7 @@ __device__ __forceinline__ bool dense_collapse(const Lds<V> &L, uint32_t pid, V 
     const uint32_t lane = __lane_id();
     uint64_t act = __ballot(live);
 #pragma unroll 1
-    for (int it = 0; it < 2 && act; ++it) {
+    for (int it = 0; it < 2 && __popcll(act) >= 24; ++it) {  // a group is a subset of act
         uint32_t leader = (uint32_t)__builtin_ctzll(act);
         uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pid, leader);
         uint64_t m = __ballot(live && pid == p0);
