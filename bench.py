@@ -54,14 +54,14 @@ HBM_PEAK_GBS = 8000.0
 # `src` is the sha256 of the render sources.
 MEASURED_TRAFFIC = {
     # profiles/basic_dedup_796M_buildings_1080p.md (one dispatch each)
-    ("k_basic", 796_000_000): {"src": "00ddcf7b7882eddca658ecdcd4a705793024496e4693b4758a73a62d8350eda6",
-                                "fetch_bytes": 8421946 * 2048, "write_bytes": 23437392 * 1024},
-    ("k_dedup<u64>", 796_000_000): {"src": "00ddcf7b7882eddca658ecdcd4a705793024496e4693b4758a73a62d8350eda6",
-                                     "fetch_bytes": 6218808 * 2048, "write_bytes": 355971 * 1024},
+    ("k_basic", 796_000_000): {"src": "027b45a3b7d130bdb21eda4127b5914f71523b5c473914333bc2e1251e44a534",
+                                "fetch_bytes": 8425234 * 2048, "write_bytes": 23437392 * 1024},
+    ("k_dedup<u64>", 796_000_000): {"src": "027b45a3b7d130bdb21eda4127b5914f71523b5c473914333bc2e1251e44a534",
+                                     "fetch_bytes": 6218809 * 2048, "write_bytes": 355971 * 1024},
     # profiles/render_terrain100M_1080p.md (averaged over the three orders)
-    ("k_basic", 100_000_000): {"src": "00ddcf7b7882eddca658ecdcd4a705793024496e4693b4758a73a62d8350eda6",
-                                "fetch_bytes": 890316 * 2048, "write_bytes": 1034719 * 1024},
-    ("k_dedup<u64>", 100_000_000): {"src": "00ddcf7b7882eddca658ecdcd4a705793024496e4693b4758a73a62d8350eda6",
+    ("k_basic", 100_000_000): {"src": "027b45a3b7d130bdb21eda4127b5914f71523b5c473914333bc2e1251e44a534",
+                                "fetch_bytes": 890212 * 2048, "write_bytes": 1034719 * 1024},
+    ("k_dedup<u64>", 100_000_000): {"src": "027b45a3b7d130bdb21eda4127b5914f71523b5c473914333bc2e1251e44a534",
                                      "fetch_bytes": 781307 * 2048, "write_bytes": 106438 * 1024},
 }
 
