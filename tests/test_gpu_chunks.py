@@ -9,8 +9,10 @@ from paper_2104_07526_amd import pcr, synth
 pytestmark = pytest.mark.gpu
 
 VARIANTS = [pcr.BASIC, pcr.DEDUP, pcr.HQ]
+# grid 1: one workgroup walks every chunk; grid 300000: clamped to 2^17 workgroups,
+# most of which have no tile.
 SHAPES = [None, {"ppt": 1, "wg": 64}, {"ppt": 4, "wg": 1024}, {"ppt": 16, "wg": 256}, {"ppt": 8, "grid": 8},
-          {"ppt": 2, "wg": 128, "grid": 13}]
+          {"ppt": 2, "wg": 128, "grid": 13}, {"ppt": 4, "grid": 1}, {"ppt": 4, "grid": 300000}]
 
 
 def chunk_sizes(rng, n_chunks, mean):
