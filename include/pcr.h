@@ -230,7 +230,7 @@ typedef struct pcr_chunk {
 size_t pcr_chunks_scratch_bytes(uint32_t nchunks);
 
 /* Renders many separate point buffers into one framebuffer with one
- * persistent launch per geometry pass (Sec. 5.4: level-of-detail structures
+ * launch per geometry pass (Sec. 5.4: level-of-detail structures
  * draw thousands of small buffers per frame; per-buffer dispatches are what
  * makes them slow).  The result is the frame of the concatenation of the
  * chunks (basic, dedup and HQ alike; the order of points does not change a

@@ -274,7 +274,7 @@ def chunk_table(chunks, device="cuda"):
 
 def render_chunks(table, nchunks, mvp, w, h, variant, fb, scratch=None, tune=None, stream=None):
     """Renders the first ``nchunks`` records of a device chunk table into fb
-    (one persistent launch per geometry pass).  Returns the scratch buffer."""
+    (one launch per geometry pass).  Returns the scratch buffer."""
     import torch
     if scratch is None:
         scratch = torch.empty(max(chunks_scratch_bytes(nchunks), 256), dtype=torch.uint8, device=fb.device)
