@@ -39,7 +39,6 @@ __device__ __forceinline__ float unord(uint32_t k) {
 __global__ __launch_bounds__(64) void k_bbox_init(uint32_t *bb) {
     if (threadIdx.x < 3) bb[threadIdx.x] = 0xFFFFFFFFu;       // min
     else if (threadIdx.x < 6) bb[threadIdx.x] = 0u;           // max
-    else if (threadIdx.x == 8) bb[8] = 0u;                    // rank of the partial batch
 }
 
 // Each step a thread has kBboxLoads points in flight (consecutive threads on
@@ -380,38 +379,39 @@ __global__ __launch_bounds__(256) void k_gather(const u32x4 *__restrict__ in, co
     }
 }
 
-// Rank (position in the shuffled batch order) of the last, possibly partial,
-// batch.
-__global__ __launch_bounds__(256) void k_find_last(const uint32_t *__restrict__ order, uint64_t nb,
-                                                   uint32_t *__restrict__ r_last) {
+// Rank (position in the shuffled batch order) of every batch: rank[order[r]] = r.
+__global__ __launch_bounds__(256) void k_batch_rank(const uint32_t *__restrict__ order, uint64_t nb,
+                                                    uint32_t *__restrict__ rank) {
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nb; r += stride)
-        if (order[r] == nb - 1) *r_last = (uint32_t)r;
+    for (uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nb; r += stride) {
+        const uint32_t b = order[r];
+        if (b < nb) rank[b] = (uint32_t)r;  // always taken for a permutation
+    }
 }
 
-// Output position j = start(r) + k for rank r, k < len(batch); batches before
-// the partial one start at r * batch, those after it `batch - len_last`
-// earlier.
+// Batch b (Morton positions [b * batch, b * batch + len)) goes to rank r =
+// rank[b]: output position start(r) + k, where batches before the partial
+// last one start at r * batch and those after it `batch - len_last` earlier.
+// Workgroups take batches in Morton order, so consecutive workgroups read
+// neighbouring points of the source (its pages stay in the TLB) and write
+// whole batches to scattered places.
 __global__ __launch_bounds__(256) void k_gather_batches(const u32x4 *__restrict__ in,
                                                         const uint32_t *__restrict__ morton,
-                                                        const uint32_t *__restrict__ order, uint64_t n,
+                                                        const uint32_t *__restrict__ rank, uint64_t n,
                                                         uint64_t nb, uint32_t batch,
-                                                        const uint32_t *__restrict__ r_last,
                                                         u32x4 *__restrict__ out, uint32_t *__restrict__ perm_out) {
     const uint64_t len_last = n - (nb - 1) * batch;
-    const uint64_t rl = *r_last;
-    uint64_t total = nb * batch;
-    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
-        uint64_t r = t / batch, k = t - r * batch;
-        uint64_t b = order[r];
-        uint64_t len = b == nb - 1 ? len_last : batch;
-        if (b >= nb || k >= len) continue;
-        uint64_t start = r * batch - (r > rl ? batch - len_last : 0);
-        uint32_t s = morton[b * batch + k];
-        if (start + k >= n || s >= n) continue;  // never taken for permutations
-        out[start + k] = in[s];
-        if (perm_out) perm_out[start + k] = s;
+    const uint64_t rl = rank[nb - 1];
+    for (uint64_t b = blockIdx.x; b < nb; b += gridDim.x) {
+        const uint64_t r = rank[b];
+        const uint64_t len = b == nb - 1 ? len_last : batch;
+        const uint64_t start = r * batch - (r > rl ? batch - len_last : 0);
+        for (uint32_t k = threadIdx.x; k < len; k += blockDim.x) {
+            const uint32_t src = morton[b * batch + k];
+            if (start + k >= n || src >= n) continue;  // never taken for permutations
+            out[start + k] = in[src];
+            if (perm_out) perm_out[start + k] = src;
+        }
     }
 }
 
@@ -513,7 +513,7 @@ extern "C" int pcr_reorder(const pcr_point *in, pcr_point *out, uint32_t *perm_o
     const u32x4 *pin = (const u32x4 *)in;
     u32x4 *pout = (u32x4 *)out;
     char *p = (char *)scratch;
-    uint32_t *word = (uint32_t *)p;  // bbox[6] / r_last
+    uint32_t *word = (uint32_t *)p;  // bbox[6]
     p += 256;
     SortBufs sb;
     p = carve_sort(p, n, sb);
@@ -551,9 +551,11 @@ extern "C" int pcr_reorder(const pcr_point *in, pcr_point *out, uint32_t *perm_o
     PCR_LAUNCHED();
     rc = radix_sort(bs, nb, 64, s);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_find_last, dim3(gn), dim3(256), 0, s, bs.v0, nb, word + 8);
-    hipLaunchKernelGGL(k_gather_batches, dim3(grid_for(nb * batch)), dim3(256), 0, s, pin, sb.v0, bs.v0, n, nb,
-                       batch, word + 8, pout, perm_out);
+    // bs.v1 is free after the sort (an even number of passes ends in bs.v0)
+    hipLaunchKernelGGL(k_batch_rank, dim3(gn), dim3(256), 0, s, bs.v0, nb, bs.v1);
+    const uint32_t gwg = (uint32_t)(nb < 65536 ? nb : 65536);
+    hipLaunchKernelGGL(k_gather_batches, dim3(gwg), dim3(256), 0, s, pin, sb.v0, bs.v1, n, nb, batch, pout,
+                       perm_out);
     PCR_LAUNCHED();
     return PCR_OK;
 }
