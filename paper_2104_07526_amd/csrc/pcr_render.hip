@@ -133,7 +133,9 @@ __device__ __forceinline__ bool wave_reduce(uint32_t pid, V val, bool live) {
 // Sums of the HQ colour pass: lanes that share the first live lane's pixel
 // hand their red, green, blue and count to that lane (the all-lanes-equal
 // reduction of Sec. 3.3 applied to integer sums; exact because + commutes),
-// for up to two leaders per wavefront.  A wavefront adds at most 64 values of
+// for up to two leaders per wavefront, each with a group of at least 16 lanes
+// (smaller groups cost more in the reduction than the LDS adds they save:
+// measured on HQ frames and batches).  A wavefront adds at most 64 values of
 // at most 255, so two channels share one 32-bit word (16 bits each) without
 // carries; the leader unpacks them into the (r<<32|g, b<<32|count) words.
 // Must be called by the whole wave.
@@ -141,11 +143,11 @@ __device__ __forceinline__ void wave_group_sums(uint32_t pid, uint32_t rgba, u64
     const uint32_t lane = __lane_id();
     uint64_t act = __ballot(live);
 #pragma unroll 1
-    for (int it = 0; it < 2 && __popcll(act) >= 4; ++it) {  // a group is a subset of act
+    for (int it = 0; it < 2 && __popcll(act) >= 16; ++it) {  // a group is a subset of act
         uint32_t leader = (uint32_t)__builtin_ctzll(act);
         uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pid, leader);
         uint64_t m = __ballot(live && pid == p0);
-        if (__popcll(m) < 4) break;
+        if (__popcll(m) < 16) break;
         bool in = (m >> lane) & 1ull;
         const uint32_t w0 = (rgba & 0xFFu) | (rgba & 0xFF00u) << 8;    // r | g << 16
         const uint32_t w1 = ((rgba >> 16) & 0xFFu) | 0x10000u;         // b | 1 << 16
