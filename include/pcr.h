@@ -87,16 +87,18 @@ enum { PCR_BASIC = 0, PCR_DEDUP = 1, PCR_HQ = 2 };
  *                 atomic: the lanes sharing a leader lane's pixel keep their
  *                 minimum (the all-lanes-equal case of Sec. 3.3, for up to
  *                 two leaders with 24 or more lanes each); without PCR_F_LDS, neighbouring lane pairs
- *                 then merge as well (Sec. 3.3).  For PCR_HQ it applies to
- *                 the depth pass.
+ *                 then merge as well (Sec. 3.3).  For PCR_HQ without
+ *                 PCR_F_LDS it applies to the depth pass, and the leader
+ *                 groups also pool their colour sums in the colour pass.
  *   PCR_F_REDUCE_WAVE / PCR_F_REDUCE_PAIR  one of PCR_F_REDUCE's two steps
  *                 alone: the leader groups, or the neighbouring pairs (the
  *                 latter only without PCR_F_LDS, else PCR_EINVAL).  Both
  *                 bits = PCR_F_REDUCE.
  *   PCR_F_LDS     merge all equal pixels of a workgroup's tile in an LDS hash
  *                 table before the atomics (Sec. 3.4's deduplication)
- *   PCR_F_PLAIN   none of the above (for PCR_HQ: one global atomic per sum
- *                 word, the paper's plain two-atomic colour pass)
+ *   PCR_F_PLAIN   none of the above (for PCR_HQ: every point within the
+ *                 blend window adds its own two sum words by global atomics,
+ *                 the paper's plain two-atomic colour pass)
  *   PCR_F_HQ_DEPTH / PCR_F_HQ_COLOR  (PCR_HQ) run only that pass; neither bit
  *                 = both passes in order.  Running the depth pass over several
  *                 point buffers and then the colour pass over the same buffers

@@ -664,7 +664,10 @@ __device__ __forceinline__ void add_sums(u64 *__restrict__ S, u64 *__restrict__ 
     }
 }
 
-template <int PPT, bool LDS, class Src, int SUMS = kTwoWord>
+// GROUPS: the wavefront group sums before the table or the global adds (the
+// merged paths and PCR_F_REDUCE); without them every point in the window adds
+// its own pair of words (the plain colour pass of Sec. 3.5).
+template <int PPT, bool LDS, class Src, int SUMS = kTwoWord, bool GROUPS = true>
 __device__ __forceinline__ void hq_color_tiles(const u32x4 *__restrict__ pts, Tiles tl, const View &v,
                                                const uint32_t *__restrict__ D, u64 *__restrict__ S,
                                                uint32_t hbits, Src src) {
@@ -705,7 +708,7 @@ __device__ __forceinline__ void hq_color_tiles(const u32x4 *__restrict__ pts, Ti
             bool live = (pid != kEmptyPid) & (__uint_as_float(dbs[j]) <= __uint_as_float(dref[j]) * 1.01f);
             u64 r = p[j].w & 0xFFu, g = (p[j].w >> 8) & 0xFFu, bl = (p[j].w >> 16) & 0xFFu;
             u64 rg = (r << 32) | g, ba = (bl << 32) | 1u;
-            wave_group_sums(pid, p[j].w, rg, ba, live);
+            if (GROUPS) wave_group_sums(pid, p[j].w, rg, ba, live);
             if (!live) continue;
             if (!LDS) {
                 add_sums<SUMS>(S, F, pid, rg, ba);
@@ -737,11 +740,11 @@ __device__ __forceinline__ void hq_color_tiles(const u32x4 *__restrict__ pts, Ti
     }
 }
 
-template <int PPT, bool LDS, class Src, int SUMS = kTwoWord>
+template <int PPT, bool LDS, class Src, int SUMS = kTwoWord, bool GROUPS = true>
 __global__ __launch_bounds__(1024) void k_hq_color(const u32x4 *__restrict__ pts, Tiles tl, View v,
                                                    const uint32_t *__restrict__ D,
                                                    u64 *__restrict__ S, uint32_t hbits, Src src) {
-    hq_color_tiles<PPT, LDS, Src, SUMS>(pts, tl, v, D, S, hbits, src);
+    hq_color_tiles<PPT, LDS, Src, SUMS, GROUPS>(pts, tl, v, D, S, hbits, src);
 }
 
 // Single-view passes driven by a batch plan's table: the view is read on the
@@ -1199,13 +1202,13 @@ inline int sums_layout(uint32_t flags) {
 
 template <int P>
 struct ColorL {
-    template <bool LDS, int SUMS>
+    template <bool LDS, int SUMS, bool GROUPS = true>
     static int go(const Launch &L, const Tiles &tl, uint32_t grid, const uint32_t *D, u64 *S, uint32_t hb,
                   size_t sm) {
         if (LDS)
-            if (int rc = allow_lds((const void *)&k_hq_color<P, LDS, FlatSrc, SUMS>, sm)) return rc;
-        hipLaunchKernelGGL((k_hq_color<P, LDS, FlatSrc, SUMS>), dim3(grid), dim3(L.sh.wg), sm, L.s, L.pts, tl, L.v, D,
-                           S, hb, FlatSrc{});
+            if (int rc = allow_lds((const void *)&k_hq_color<P, LDS, FlatSrc, SUMS, GROUPS>, sm)) return rc;
+        hipLaunchKernelGGL((k_hq_color<P, LDS, FlatSrc, SUMS, GROUPS>), dim3(grid), dim3(L.sh.wg), sm, L.s, L.pts, tl,
+                           L.v, D, S, hb, FlatSrc{});
         PCR_LAUNCHED();
         return PCR_OK;
     }
@@ -1224,9 +1227,16 @@ struct ColorL {
             if (sums == kRobust) return go<true, kRobust>(L, tl, grid, D, S, hb, sm);
             return go<true, kTwoWord>(L, tl, grid, D, S, hb, sm);
         }
-        if (sums == kPacked) return go<false, kPacked>(L, tl, grid, D, S, 1u, 0);
-        if (sums == kRobust) return go<false, kRobust>(L, tl, grid, D, S, 1u, 0);
-        return go<false, kTwoWord>(L, tl, grid, D, S, 1u, 0);
+        // Without the table the group sums run only with the leader-group
+        // reduction (PCR_F_REDUCE or PCR_F_REDUCE_WAVE).
+        if (reduce_mode(L.flags) & 1) {
+            if (sums == kPacked) return go<false, kPacked, true>(L, tl, grid, D, S, 1u, 0);
+            if (sums == kRobust) return go<false, kRobust, true>(L, tl, grid, D, S, 1u, 0);
+            return go<false, kTwoWord, true>(L, tl, grid, D, S, 1u, 0);
+        }
+        if (sums == kPacked) return go<false, kPacked, false>(L, tl, grid, D, S, 1u, 0);
+        if (sums == kRobust) return go<false, kRobust, false>(L, tl, grid, D, S, 1u, 0);
+        return go<false, kTwoWord, false>(L, tl, grid, D, S, 1u, 0);
     }
 };
 
