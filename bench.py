@@ -54,15 +54,15 @@ HBM_PEAK_GBS = 8000.0
 # `src` is the sha256 of the render sources.
 MEASURED_TRAFFIC = {
     # profiles/basic_dedup_796M_buildings_1080p.md (one dispatch each)
-    ("k_basic", 796_000_000): {"src": "72416c9f119b7f342d66a63ebc6764204ca0d95c608e7e4a96d9ae5a21a90b36",
-                                "fetch_bytes": 8419395 * 2048, "write_bytes": 23437392 * 1024},
-    ("k_dedup<u64>", 796_000_000): {"src": "72416c9f119b7f342d66a63ebc6764204ca0d95c608e7e4a96d9ae5a21a90b36",
-                                     "fetch_bytes": 6218810 * 2048, "write_bytes": 355971 * 1024},
+    ("k_basic", 796_000_000): {"src": "2765e9d216a05e69f86ac103b2d1b38b8482b79a5b9037da3e80a1296a571519",
+                                "fetch_bytes": 8418548 * 2048, "write_bytes": 23437392 * 1024},
+    ("k_dedup<u64>", 796_000_000): {"src": "2765e9d216a05e69f86ac103b2d1b38b8482b79a5b9037da3e80a1296a571519",
+                                     "fetch_bytes": 6218809 * 2048, "write_bytes": 355971 * 1024},
     # profiles/render_terrain100M_1080p.md (averaged over the three orders)
-    ("k_basic", 100_000_000): {"src": "72416c9f119b7f342d66a63ebc6764204ca0d95c608e7e4a96d9ae5a21a90b36",
-                                "fetch_bytes": 890428 * 2048, "write_bytes": 1034719 * 1024},
-    ("k_dedup<u64>", 100_000_000): {"src": "72416c9f119b7f342d66a63ebc6764204ca0d95c608e7e4a96d9ae5a21a90b36",
-                                     "fetch_bytes": 781307 * 2048, "write_bytes": 106438 * 1024},
+    ("k_basic", 100_000_000): {"src": "2765e9d216a05e69f86ac103b2d1b38b8482b79a5b9037da3e80a1296a571519",
+                                "fetch_bytes": 890192 * 2048, "write_bytes": 1034719 * 1024},
+    ("k_dedup<u64>", 100_000_000): {"src": "2765e9d216a05e69f86ac103b2d1b38b8482b79a5b9037da3e80a1296a571519",
+                                     "fetch_bytes": 781308 * 2048, "write_bytes": 106438 * 1024},
 }
 
 
