@@ -31,3 +31,15 @@ def test_every_profile_names_runnable_commands():
             assert leg is None or leg.group(1) in legs, (f, c)
             assert "_work" not in c, (f, c)
         assert "| kernel |" in text, f"{f}: no kernel table"
+
+
+def test_measured_traffic_matches_the_render_sources():
+    """The bench line's measured traffic (FETCH_SIZE / WRITE_SIZE of the
+    profiled kernels) was taken from the current render sources; the bench
+    reports null traffic otherwise."""
+    import bench
+    sha = bench.render_sources_sha()
+    assert bench.MEASURED_TRAFFIC, "no measured traffic"
+    for key, rec in bench.MEASURED_TRAFFIC.items():
+        assert rec["src"] == sha, key
+        assert bench.traffic_for(*key) == rec["fetch_bytes"] + rec["write_bytes"]
