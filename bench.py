@@ -394,9 +394,9 @@ def leg_main(args):
                    "atomic_probe_G_per_s": {**probe, "footprint_MB": round(8 * words / 1e6, 2)},
                    "reorder_ms": round(rms, 2),
                    "terrain_100M": terrain,
-                   "note": "The north-star bar (the basic rasterizer at >= 60% of HBM bandwidth on the 796M cloud) "
+                   "note": "The 60% bar (the basic rasterizer at >= 60% of HBM bandwidth on the 796M cloud) "
                            "is not met: k_basic issues one device-scope 64-bit atomic per visible point, which "
-                           "the chip performs memory-side at the probe's rate, far below the 500 G points/s "
+                           "the chip performs memory-side at the probe's rate, far below the 300 G points/s "
                            "that 60% of HBM would need. The deduplicating kernel (detail) is the form that "
                            "approaches the HBM roofline.",
                    "wall_s_timed": round(wall, 3),
