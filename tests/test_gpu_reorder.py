@@ -31,7 +31,7 @@ def gpu_reorder(pts, order, batch=128, seed=0):
 
 
 @pytest.mark.parametrize("order", ORDERS)
-@pytest.mark.parametrize("n", [1, 2, 127, 128, 129, 4095, 4096, 4097, 65_537, 300_001])
+@pytest.mark.parametrize("n", [1, 2, 127, 128, 129, 4095, 4096, 4097, 8191, 8192, 8193, 16_385, 65_537, 300_001])
 def test_perm_matches_oracle(orc, order, n):
     pts = cloud(n, seed=n)
     exp = orc.reorder(pts, order, 128, 77)
