@@ -27,6 +27,10 @@ FLAGS = [
     "-ffp-contract=off", "-fno-fast-math", "-fhip-fp32-correctly-rounded-divide-sqrt",
     "-fno-gpu-flush-denormals-to-zero",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # The superword vectorizer packed the viewport test of one unrolled point
+    # of the render loops into 16-bit vector bit operations (about a dozen
+    # extra vector instructions per such point); scalar lane masks are cheaper.
+    "-fno-slp-vectorize",
     "-Wall", "-Wno-unused-result",
     "-I", os.path.join(ROOT, "include"),
 ]

@@ -69,12 +69,14 @@ __device__ __forceinline__ Clip clip(const View &v, float x, float y, float z) {
     return c;
 }
 
-// True only for points that finish() culls for certain: behind the camera, or
-// more than 0.1% outside the view cone in clip space (the rounding of the
-// exact path is below 1e-6 relative).  NaN compares false: not certain.
-__device__ __forceinline__ bool surely_culled(const Clip &c) {
-    float lim = c.cw * 1.001f;  // >= 0 whenever the first test fails
-    return c.cw <= 0.0f || __builtin_fabsf(c.cx) > lim || __builtin_fabsf(c.cy) > lim;
+// Lanes of the wavefront whose points finish() culls for certain: behind the
+// camera, or more than 0.1% outside the view cone in clip space (the rounding
+// of the exact path is below 1e-6 relative).  NaN compares false: not certain.
+// One ballot per compare: the lane mask of the combined predicate was moved
+// through a vector register in some kernels.  Must be called by the whole wave.
+__device__ __forceinline__ uint64_t surely_culled(const Clip &c) {
+    const float lim = c.cw * 1.001f;  // >= 0 whenever the first test fails
+    return __ballot(c.cw <= 0.0f) | __ballot(__builtin_fabsf(c.cx) > lim) | __ballot(__builtin_fabsf(c.cy) > lim);
 }
 
 // Correctly rounded 1/w by one Newton-Raphson step: r = v_rcp_f32(w) (the
@@ -119,14 +121,16 @@ __device__ __forceinline__ uint32_t project(const View &v, float x, float y, flo
 }
 
 // Projection with the wavefront-level early out: returns kEmptyPid for every
-// lane when no lane of the wavefront can be visible (`live` false = lane past
-// the end of the buffer).  Must be called by the whole wavefront.
-__device__ __forceinline__ uint32_t project_wave(const View &v, const u32x4 &p, bool live, uint32_t &dbits) {
+// lane when no lane of the wavefront can be visible.  `live`: lane mask of the
+// lanes that hold a point (the others are past the end of the buffer), passed
+// as a mask so that it stays in scalar registers across the callers' loops.
+// Must be called by the whole wavefront.
+__device__ __forceinline__ uint32_t project_wave(const View &v, const u32x4 &p, uint64_t live, uint32_t &dbits) {
     Clip c = clip(v, __uint_as_float(p.x), __uint_as_float(p.y), __uint_as_float(p.z));
     dbits = __float_as_uint(c.cw);
-    if (__ballot(live && !surely_culled(c)) == 0) return kEmptyPid;
+    if ((live & ~surely_culled(c)) == 0) return kEmptyPid;
     uint32_t pid = finish(v, c, dbits);
-    return live ? pid : kEmptyPid;
+    return __builtin_amdgcn_inverse_ballot_w64(live) ? pid : kEmptyPid;
 }
 
 // Non-temporal 16-byte point load, addressed as global memory (point

@@ -53,6 +53,13 @@ __device__ __forceinline__ uint32_t dpp32(uint32_t x, uint32_t ident) {
 
 __device__ __forceinline__ uint32_t vmin(uint32_t a, uint32_t b) { return b < a ? b : a; }
 
+// Set lanes of a lane mask, counted as two 32-bit halves: compared with a
+// constant, a single 64-bit count is widened by the compiler into a 64-bit
+// vector compare, where the halves stay on the scalar unit.
+__device__ __forceinline__ uint32_t lanes_in(uint64_t m) {
+    return (uint32_t)__builtin_popcount((uint32_t)m) + (uint32_t)__builtin_popcount((uint32_t)(m >> 32));
+}
+
 // Minimum over the wavefront (uniform result).
 __device__ __forceinline__ uint32_t wave_min(uint32_t x) {
     const uint32_t I = ~0u;
@@ -100,29 +107,41 @@ __device__ __forceinline__ V lane_pair(V x) {
     }
 }
 
+// Lane of a uniform lane mask as a per-lane predicate (no vector work: the
+// mask itself is the predicate).
+__device__ __forceinline__ bool lane_in(uint64_t mask) { return __builtin_amdgcn_inverse_ballot_w64(mask); }
+
+// The group loops below keep `live` as a uniform lane mask and return it
+// through lane_in(): updated per lane inside the loop, the flag was kept in a
+// vector register (a select, a mask and a compare per group).
+
 // RED: bit 0 = leader groups (all lanes equal), bit 1 = neighbouring pairs.
+// Must be called by the whole wave.
 template <typename V, int RED>
 __device__ __forceinline__ bool wave_reduce(uint32_t pid, V val, bool live) {
     // Leader groups: the lanes sharing the first remaining live lane's pixel
     // keep only their minimum (with every live lane in one group this is the
     // all-lanes-equal case of Sec. 3.3).  Up to two groups of at least 24
     // lanes; a wavefront spread over several pixels leaves after one ballot.
-    const uint32_t lane = __lane_id();
-    uint64_t act = (RED & 1) ? __ballot(live) : 0ull;
-    // A group is a subset of act: with fewer than 24 lanes left none can form.
+    if (RED & 1) {
+        uint64_t act = __ballot(live);  // live lanes not in a group yet
+        uint64_t keep = act;            // live lanes
+        // A group is a subset of act: with fewer than 24 lanes left none can form.
 #pragma unroll 1
-    for (int it = 0; it < 2 && __popcll(act) >= 24; ++it) {
-        uint32_t leader = (uint32_t)__builtin_ctzll(act);
-        uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pid, leader);
-        uint64_t m = __ballot(live && pid == p0);
-        if (__popcll(m) < 24) break;
-        bool in = (m >> lane) & 1ull;
-        const uint32_t md = wave_min(in ? depth_of(val) : ~0u);
-        if (in) live = depth_of(val) == md;  // the group's minimum is among these lanes
-        act &= ~m;
+        for (int it = 0; it < 2 && lanes_in(act) >= 24u; ++it) {
+            uint32_t leader = (uint32_t)__builtin_ctzll(act);
+            uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pid, leader);
+            uint64_t m = __ballot(pid == p0) & act;  // the group: live lanes on pixel p0
+            if (lanes_in(m) < 24u) break;
+            const uint32_t md = wave_min(lane_in(m) ? depth_of(val) : ~0u);
+            keep &= ~m | __ballot(depth_of(val) == md);  // the group's minimum is among these lanes
+            act &= ~m;
+        }
+        live = lane_in(keep);
     }
     if (!(RED & 2)) return live;
     // Neighbouring lane pairs merge (Sec. 3.3, pairs).
+    const uint32_t lane = __lane_id();
     uint32_t ppid = lane_pair(live ? pid : kEmptyPid);
     V pval = lane_pair(val);
     bool same = live && ppid == pid;
@@ -138,30 +157,29 @@ __device__ __forceinline__ bool wave_reduce(uint32_t pid, V val, bool live) {
 // measured on HQ frames and batches).  A wavefront adds at most 64 values of
 // at most 255, so two channels share one 32-bit word (16 bits each) without
 // carries; the leader unpacks them into the (r<<32|g, b<<32|count) words.
-// Must be called by the whole wave.
-__device__ __forceinline__ void wave_group_sums(uint32_t pid, uint32_t rgba, u64 &rg, u64 &ba, bool &live) {
-    const uint32_t lane = __lane_id();
-    uint64_t act = __ballot(live);
+// Takes and returns the lane mask of the live lanes.  Must be called by the
+// whole wave.
+__device__ __forceinline__ uint64_t wave_group_sums(uint32_t pid, uint32_t rgba, u64 &rg, u64 &ba, uint64_t act) {
+    uint64_t keep = act;
 #pragma unroll 1
-    for (int it = 0; it < 2 && __popcll(act) >= 16; ++it) {  // a group is a subset of act
+    for (int it = 0; it < 2 && lanes_in(act) >= 16u; ++it) {  // a group is a subset of act
         uint32_t leader = (uint32_t)__builtin_ctzll(act);
         uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pid, leader);
-        uint64_t m = __ballot(live && pid == p0);
-        if (__popcll(m) < 16) break;
-        bool in = (m >> lane) & 1ull;
+        uint64_t m = __ballot(pid == p0) & act;
+        if (lanes_in(m) < 16u) break;
+        const bool in = lane_in(m);
         const uint32_t w0 = (rgba & 0xFFu) | (rgba & 0xFF00u) << 8;    // r | g << 16
         const uint32_t w1 = ((rgba >> 16) & 0xFFu) | 0x10000u;         // b | 1 << 16
         const uint32_t a = wave_sum(in ? w0 : 0u), b = wave_sum(in ? w1 : 0u);
-        if (in) {
-            if (lane == leader) {
-                rg = (u64)(a & 0xFFFFu) << 32 | (a >> 16);
-                ba = (u64)(b & 0xFFFFu) << 32 | (b >> 16);
-            } else {
-                live = false;
-            }
+        const uint64_t lead = 1ull << leader;  // the leader is in the group
+        if (lane_in(lead)) {
+            rg = (u64)(a & 0xFFFFu) << 32 | (a >> 16);
+            ba = (u64)(b & 0xFFFFu) << 32 | (b >> 16);
         }
+        keep &= ~m | lead;
         act &= ~m;
     }
+    return keep;
 }
 
 // ---------------------------------------------------------------------------
@@ -249,22 +267,21 @@ __device__ __forceinline__ void lds_barrier() {
 // test (its value is already small).  Up to two groups.
 template <typename V>
 __device__ __forceinline__ bool dense_collapse(const Lds<V> &L, uint32_t pid, V val, bool live) {
-    const uint32_t lane = __lane_id();
     uint64_t act = __ballot(live);
+    uint64_t keep = act;
 #pragma unroll 1
-    for (int it = 0; it < 2 && __popcll(act) >= 24; ++it) {  // a group is a subset of act
+    for (int it = 0; it < 2 && lanes_in(act) >= 24u; ++it) {  // a group is a subset of act
         uint32_t leader = (uint32_t)__builtin_ctzll(act);
         uint32_t p0 = (uint32_t)__builtin_amdgcn_readlane((int)pid, leader);
-        uint64_t m = __ballot(live && pid == p0);
-        if (__popcll(m) < 24) break;
+        uint64_t m = __ballot(pid == p0) & act;
+        if (lanes_in(m) < 24u) break;
         act &= ~m;
         uint32_t t0 = L.tag[L.home(p0)];
         if (t0 == p0) continue;  // slot exists: the early test filters
-        bool in = (m >> lane) & 1ull;
-        const uint32_t md = wave_min(in ? depth_of(val) : ~0u);
-        if (in) live = depth_of(val) == md;  // the group's minimum is among these lanes
+        const uint32_t md = wave_min(lane_in(m) ? depth_of(val) : ~0u);
+        keep &= ~m | __ballot(depth_of(val) == md);  // the group's minimum is among these lanes
     }
-    return live;
+    return lane_in(keep);
 }
 
 inline size_t lds_bytes(uint32_t hbits, size_t vbytes) {
@@ -465,7 +482,7 @@ __global__ __launch_bounds__(1024) void k_basic(const u32x4 *__restrict__ pts, T
             for (int j = 0; j < PPT; ++j) {
                 uint32_t dbits;
                 const uint32_t k = kSub ? k0 + j : j * wg + threadIdx.x;
-                uint32_t pid = project_wave(v, p[j], k < lim, dbits);
+                uint32_t pid = project_wave(v, p[j], __ballot(k < lim), dbits);
                 u64 key = make_key(dbits, p[j].w);
                 bool w = pid != kEmptyPid;
                 if (adapt && c == 0) {
@@ -519,7 +536,7 @@ __device__ __forceinline__ void dedup_tiles(const u32x4 *__restrict__ pts, Tiles
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             uint32_t dbits;
-            uint32_t pid = project_wave(v, p[j], (uint32_t)(j * wg + threadIdx.x) < lim, dbits);
+            uint32_t pid = project_wave(v, p[j], __ballot((uint32_t)(j * wg + threadIdx.x) < lim), dbits);
             V val;
             if constexpr (sizeof(V) == 8)
                 val = make_key(dbits, p[j].w);
@@ -580,7 +597,7 @@ __global__ __launch_bounds__(1024) void k_hq_depth(const u32x4 *__restrict__ pts
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             uint32_t dbits;
-            uint32_t pid = project_wave(v, p[j], (uint32_t)(j * wg + threadIdx.x) < lim, dbits);
+            uint32_t pid = project_wave(v, p[j], __ballot((uint32_t)(j * wg + threadIdx.x) < lim), dbits);
             bool w = pid != kEmptyPid;
             if (RED) w = wave_reduce<uint32_t, RED>(pid, dbits, w);
             if (EARLYZ && w) w = dbits < peek_u32(D + pid);
@@ -697,19 +714,21 @@ __device__ __forceinline__ void hq_color_tiles(const u32x4 *__restrict__ pts, Ti
         // to back (one round trip for the tile instead of one per point).
         uint32_t pids[PPT], dbs[PPT], dref[PPT];
 #pragma unroll
-        for (int j = 0; j < PPT; ++j) pids[j] = project_wave(v, p[j], (uint32_t)(j * wg + threadIdx.x) < lim, dbs[j]);
+        for (int j = 0; j < PPT; ++j) pids[j] = project_wave(v, p[j], __ballot((uint32_t)(j * wg + threadIdx.x) < lim), dbs[j]);
 #pragma unroll
         for (int j = 0; j < PPT; ++j) dref[j] = D[pids[j] != kEmptyPid ? pids[j] : 0u];
 #pragma unroll
         for (int j = 0; j < PPT; ++j) {
             const uint32_t pid = pids[j];
-            // branch-free '&': for an empty pixel dref is pixel 0's depth and the
-            // result is false either way
-            bool live = (pid != kEmptyPid) & (__uint_as_float(dbs[j]) <= __uint_as_float(dref[j]) * 1.01f);
+            // live lanes: a pixel, and a depth within 1% of the closest (for an
+            // empty pixel dref is pixel 0's depth, and the lane is out either
+            // way); ballots of single compares, since the lane mask of a
+            // combined predicate was moved through a vector register
+            const uint64_t lm = __ballot(pid != kEmptyPid) &
+                                __ballot(__uint_as_float(dbs[j]) <= __uint_as_float(dref[j]) * 1.01f);
             u64 r = p[j].w & 0xFFu, g = (p[j].w >> 8) & 0xFFu, bl = (p[j].w >> 16) & 0xFFu;
             u64 rg = (r << 32) | g, ba = (bl << 32) | 1u;
-            if (GROUPS) wave_group_sums(pid, p[j].w, rg, ba, live);
-            if (!live) continue;
+            if (!lane_in(GROUPS ? wave_group_sums(pid, p[j].w, rg, ba, lm) : lm)) continue;
             if (!LDS) {
                 add_sums<SUMS>(S, F, pid, rg, ba);
                 continue;
@@ -793,14 +812,14 @@ __global__ __launch_bounds__(1024) void k_view_pass(const u32x4 *__restrict__ pt
 // so the table's minimum is the smallest depth and the dense-group collapse
 // compares depths as for keys.
 template <int PPT>
-__device__ __forceinline__ void group_tile_closest(Lds<u64> &L, const u32x4 (&p)[PPT], uint32_t lim, const View &v,
-                                                   bool hq, u64 *__restrict__ fb, uint32_t *__restrict__ D,
-                                                   uint32_t &par) {
+__device__ __forceinline__ void group_tile_closest(Lds<u64> &L, const u32x4 (&p)[PPT], const uint64_t (&lm)[PPT],
+                                                   const View &v, bool hq, u64 *__restrict__ fb,
+                                                   uint32_t *__restrict__ D, uint32_t &par) {
     const uint32_t wg = blockDim.x;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         uint32_t dbits;
-        const uint32_t pid = project_wave(v, p[j], (uint32_t)(j * wg + threadIdx.x) < lim, dbits);
+        const uint32_t pid = project_wave(v, p[j], lm[j], dbits);
         const u64 val = hq ? (u64)dbits << 32 : make_key(dbits, p[j].w);
         bool w = dense_collapse<u64>(L, pid, val, pid != kEmptyPid);
         if (w) {
@@ -833,23 +852,23 @@ __device__ __forceinline__ void group_tile_closest(Lds<u64> &L, const u32x4 (&p)
 
 // One tile into one HQ view's colour sums (the merged two-word colour pass).
 template <int PPT>
-__device__ __forceinline__ void group_tile_color(Lds<Sum2> &L, const u32x4 (&p)[PPT], uint32_t lim, const View &v,
-                                                 const uint32_t *__restrict__ D, u64 *__restrict__ S,
-                                                 uint32_t &par) {
+__device__ __forceinline__ void group_tile_color(Lds<Sum2> &L, const u32x4 (&p)[PPT], const uint64_t (&lm)[PPT],
+                                                 const View &v, const uint32_t *__restrict__ D,
+                                                 u64 *__restrict__ S, uint32_t &par) {
     const uint32_t wg = blockDim.x;
     uint32_t pids[PPT], dbs[PPT], dref[PPT];
 #pragma unroll
-    for (int j = 0; j < PPT; ++j) pids[j] = project_wave(v, p[j], (uint32_t)(j * wg + threadIdx.x) < lim, dbs[j]);
+    for (int j = 0; j < PPT; ++j) pids[j] = project_wave(v, p[j], lm[j], dbs[j]);
 #pragma unroll
     for (int j = 0; j < PPT; ++j) dref[j] = D[pids[j] != kEmptyPid ? pids[j] : 0u];
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
         const uint32_t pid = pids[j];
-        bool live = (pid != kEmptyPid) & (__uint_as_float(dbs[j]) <= __uint_as_float(dref[j]) * 1.01f);
+        const uint64_t lm = __ballot(pid != kEmptyPid) &
+                            __ballot(__uint_as_float(dbs[j]) <= __uint_as_float(dref[j]) * 1.01f);  // as in hq_color_tiles
         u64 r = p[j].w & 0xFFu, g = (p[j].w >> 8) & 0xFFu, bl = (p[j].w >> 16) & 0xFFu;
         u64 rg = (r << 32) | g, ba = (bl << 32) | 1u;
-        wave_group_sums(pid, p[j].w, rg, ba, live);
-        if (!live) continue;
+        if (!lane_in(wave_group_sums(pid, p[j].w, rg, ba, lm))) continue;
         const uint32_t h = L.slot(pid, par);
         if (h == kNoSlot) {
             gadd_u64(S + 2 * (u64)pid, rg);
@@ -915,6 +934,11 @@ __global__ __launch_bounds__(1024) void k_group_pass(const u32x4 *__restrict__ p
     for (; g < ng;) {
         u32x4 p[PPT];
         const uint32_t lim = FlatSrc{}.template load<PPT>(pts, t, wg, tl.n, p);
+        // lanes that hold a point, per row, as lane masks: taken next to their
+        // compares, they stay in scalar registers across the loop over views
+        uint64_t lm[PPT];
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) lm[j] = __ballot((uint32_t)(j * wg + threadIdx.x) < lim);
         const uint32_t first = (uint32_t)__builtin_amdgcn_readfirstlane((int)groups[g].first);
         const uint32_t count = (uint32_t)__builtin_amdgcn_readfirstlane((int)groups[g].count);
         for (uint32_t k = 0; k < count; ++k) {
@@ -923,9 +947,9 @@ __global__ __launch_bounds__(1024) void k_group_pass(const u32x4 *__restrict__ p
             const int variant = __builtin_amdgcn_readfirstlane(bv->variant);
             const View v = uniform_view(&bv->v);
             if constexpr (PASS == 0) {
-                group_tile_closest<PPT>(L, p, lim, v, variant == PCR_HQ, bv->fb, bv->D, par);
+                group_tile_closest<PPT>(L, p, lm, v, variant == PCR_HQ, bv->fb, bv->D, par);
             } else {
-                if (variant == PCR_HQ) group_tile_color<PPT>(L, p, lim, v, bv->D, bv->S, par);
+                if (variant == PCR_HQ) group_tile_color<PPT>(L, p, lm, v, bv->D, bv->S, par);
             }
         }
         t += gridDim.x;
@@ -1253,36 +1277,47 @@ __device__ __forceinline__ uint64_t shfl_up64(uint64_t x, uint32_t d) {
 // One workgroup of 1024 threads takes 8192 chunks per step, 8 consecutive
 // chunks per thread: the 8 records are loaded together, summed in the thread,
 // and the thread totals scanned across the workgroup; tiles hold 2^tshift
-// points (a power of two).
+// points (a power of two).  No record load sits behind a per-record branch
+// (indices past the end are clamped to the last record and their counts
+// dropped), so the 8 loads are in flight at once instead of one memory round
+// trip each; the next step's records are requested before this step's scan,
+// whose barriers order LDS only and leave them in flight.
 constexpr uint32_t kStartsPer = 8;
+
+__device__ __forceinline__ void load_chunk_records(const pcr_chunk *__restrict__ chunks, uint32_t nchunks,
+                                                   uint32_t i0, pcr_chunk (&ch)[kStartsPer]) {
+#pragma unroll
+    for (uint32_t r = 0; r < kStartsPer; ++r) ch[r] = chunks[i0 + r < nchunks ? i0 + r : nchunks - 1];
+}
 
 __global__ __launch_bounds__(1024) void k_chunk_starts(const pcr_chunk *__restrict__ chunks, uint32_t nchunks,
                                                        uint32_t tshift, uint64_t *__restrict__ start) {
     __shared__ uint64_t wtot[16];
     const uint32_t lane = threadIdx.x & 63u, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint32_t step = blockDim.x * kStartsPer;
     const uint64_t T = 1ull << tshift;
     uint64_t carry = 0;
-    for (uint32_t base = 0; base < nchunks; base += blockDim.x * kStartsPer) {
+    pcr_chunk ch[kStartsPer];
+    if (nchunks > 0) load_chunk_records(chunks, nchunks, threadIdx.x * kStartsPer, ch);
+    for (uint32_t base = 0; base < nchunks; base += step) {
         const uint32_t i0 = base + threadIdx.x * kStartsPer;
         uint64_t c[kStartsPer];
         uint64_t sum = 0;
 #pragma unroll
         for (uint32_t r = 0; r < kStartsPer; ++r) {
-            c[r] = 0;
-            if (i0 + r < nchunks) {
-                const pcr_chunk ch = chunks[i0 + r];
-                const bool ok = ch.pts != nullptr && ((uintptr_t)ch.pts & 15u) == 0 && ch.n <= PCR_CHUNK_MAX_POINTS;
-                c[r] = ok ? (ch.n + T - 1) >> tshift : 0;  // tiles of the chunk
-            }
+            const bool ok = i0 + r < nchunks && ch[r].pts != nullptr && ((uintptr_t)ch[r].pts & 15u) == 0 &&
+                            ch[r].n <= PCR_CHUNK_MAX_POINTS;
+            c[r] = ok ? (ch[r].n + T - 1) >> tshift : 0;  // tiles of the chunk
             sum += c[r];
         }
+        if (base + step < nchunks) load_chunk_records(chunks, nchunks, i0 + step, ch);  // uniform
         uint64_t x = sum;  // inclusive scan of the thread totals over the wavefront
         for (uint32_t d = 1; d < 64; d <<= 1) {
             const uint64_t y = shfl_up64(x, d);
             if (lane >= d) x += y;
         }
         if (lane == 63) wtot[wid] = x;
-        __syncthreads();
+        lds_barrier();
         uint64_t before = carry, total = carry;
         for (uint32_t k = 0; k < nw; ++k) {
             if (k < wid) before += wtot[k];
@@ -1295,7 +1330,7 @@ __global__ __launch_bounds__(1024) void k_chunk_starts(const pcr_chunk *__restri
             run += c[r];
         }
         carry = total;
-        __syncthreads();
+        lds_barrier();
     }
     if (threadIdx.x == 0) start[nchunks] = carry;
 }
