@@ -166,3 +166,64 @@ def test_many_chunks_scan():
         pcr.render(upload(host), m, W, H, variant, ref)
         torch.cuda.synchronize()
         assert torch.equal(fb, ref)
+
+
+@pytest.mark.parametrize("nchunks", [1, 4095, 4096, 4097, 12289])
+@pytest.mark.parametrize("grid", [37, 300000])
+def test_chunk_start_offsets(nchunks, grid):
+    """White-box check of the chunked launch's set-up, written to the caller's
+    scratch: words [0, nchunks] are the exclusive prefix of the chunks' tile
+    counts (skipped chunks count 0 tiles), then, at the next 256-byte boundary,
+    one 32-bit word per render workgroup holds the chunk of its first tile
+    (the last c with start[c] <= b * ceil(tiles / grid)).  Sizes straddle the
+    prefix pass's steps; the image equals the render of the kept points as one
+    buffer."""
+    import torch
+    T, ppt, wg = 256, 4, 64
+    rng = np.random.default_rng(nchunks + grid)
+    sizes = rng.integers(0, 600, nchunks)
+    pts = synth.terrain(int(sizes.sum()) + 1, seed=11)
+    whole = upload(pts)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    kind = rng.integers(0, 12, nchunks)  # 0: NULL pointer, 1: misaligned, 2: too many points, else kept
+    rows, kept = [], []
+    for c in range(nchunks):
+        a, n = int(offs[c]), int(sizes[c])
+        addr = whole.data_ptr() + 16 * a
+        if kind[c] == 0:
+            rows.append((0, n))
+        elif kind[c] == 1:
+            rows.append((addr + 8, n))
+        elif kind[c] == 2:
+            rows.append((addr, (1 << 36) + 1))
+        else:
+            rows.append((addr, n))
+            kept.append(pts[a:a + n])
+    tiles = np.array([(n + T - 1) // T if k > 2 else 0 for n, k in zip(sizes, kind)], dtype=np.int64)
+    start = np.concatenate([[0], np.cumsum(tiles)])
+    W, H = 320, 240
+    m = synth.terrain_overview(W, H)
+    fb = pcr.alloc_fb(W, H, pcr.DEDUP)
+    pcr.fb_clear(fb, W, H, pcr.DEDUP)
+    scratch = torch.full((pcr.chunks_scratch_bytes(nchunks),), 0xAB, dtype=torch.uint8, device="cuda")
+    pcr.render_chunks(pcr.chunk_table(rows), nchunks, m, W, H, pcr.DEDUP, fb, scratch=scratch,
+                      tune={"ppt": ppt, "wg": wg, "grid": grid})
+    torch.cuda.synchronize()
+    got = scratch[:8 * (nchunks + 1)].view(torch.int64).cpu().numpy()
+    np.testing.assert_array_equal(got, start)
+    g = min(grid, 1 << 17)
+    off = (8 * (nchunks + 1) + 255) // 256 * 256
+    wgc = scratch[off:off + 4 * g].view(torch.int32).cpu().numpy()
+    total = int(start[-1])
+    per = -(-total // g)
+    for b in range(g):
+        t = b * per
+        if t >= total:
+            break  # workgroups without a tile never read their word
+        assert wgc[b] == int(np.searchsorted(start, t, side="right")) - 1, b
+    ref = pcr.alloc_fb(W, H, pcr.DEDUP)
+    pcr.fb_clear(ref, W, H, pcr.DEDUP)
+    if kept:
+        pcr.render(upload(np.concatenate(kept)), m, W, H, pcr.DEDUP, ref)
+    torch.cuda.synchronize()
+    assert torch.equal(fb, ref)
