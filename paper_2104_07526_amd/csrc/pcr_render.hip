@@ -681,6 +681,24 @@ __device__ __forceinline__ void add_sums(u64 *__restrict__ S, u64 *__restrict__ 
     }
 }
 
+// Flush of a colour table into the two-word sums: two lanes per slot, one
+// word each, so that a pixel's two adds leave in one instruction and travel
+// in one memory request (adjacent words of one line); with one lane per slot
+// they were two instructions and two requests.  The lanes of a pair are
+// neighbours in one wavefront (wg is a power of two of at least 64), and each
+// reads its slot before the even lane clears the tag.
+__device__ __forceinline__ void flush_sum_pairs(Lds<Sum2> &L, u64 *__restrict__ S, uint32_t cnt, uint32_t wg) {
+    for (uint32_t k2 = threadIdx.x; k2 < 2 * cnt; k2 += wg) {
+        const uint32_t h = L.list[k2 >> 1], half = k2 & 1u;
+        const uint32_t pid = L.tag[h];
+        u64 *word = &L.val[h].rg + half;  // rg, then ba
+        const u64 x = *word;
+        *word = 0;
+        if (!half) L.tag[h] = kEmptyPid;
+        gadd_u64(S + 2 * (u64)pid + half, x);
+    }
+}
+
 // GROUPS: the wavefront group sums before the table or the global adds (the
 // merged paths and PCR_F_REDUCE); without them every point in the window adds
 // its own pair of words (the plain colour pass of Sec. 3.5).
@@ -745,14 +763,18 @@ __device__ __forceinline__ void hq_color_tiles(const u32x4 *__restrict__ pts, Ti
         lds_barrier();
         uint32_t cnt = L.count[par];
         if (threadIdx.x == 0) L.count[par ^ 1u] = 0;
-        for (uint32_t k = threadIdx.x; k < cnt; k += wg) {
-            uint32_t h = L.list[k];
-            uint32_t pid = L.tag[h];
-            Sum2 sm = L.val[h];
-            L.tag[h] = kEmptyPid;
-            L.val[h].rg = 0;
-            L.val[h].ba = 0;
-            add_sums<SUMS>(S, F, pid, sm.rg, sm.ba);
+        if constexpr (SUMS == kTwoWord) {
+            flush_sum_pairs(L, S, cnt, wg);
+        } else {
+            for (uint32_t k = threadIdx.x; k < cnt; k += wg) {
+                uint32_t h = L.list[k];
+                uint32_t pid = L.tag[h];
+                Sum2 sm = L.val[h];
+                L.tag[h] = kEmptyPid;
+                L.val[h].rg = 0;
+                L.val[h].ba = 0;
+                add_sums<SUMS>(S, F, pid, sm.rg, sm.ba);
+            }
         }
         lds_barrier();
         par ^= 1u;
@@ -881,16 +903,7 @@ __device__ __forceinline__ void group_tile_color(Lds<Sum2> &L, const u32x4 (&p)[
     lds_barrier();
     const uint32_t cnt = L.count[par];
     if (threadIdx.x == 0) L.count[par ^ 1u] = 0;
-    for (uint32_t k = threadIdx.x; k < cnt; k += wg) {
-        const uint32_t h = L.list[k];
-        const uint32_t pid = L.tag[h];
-        const Sum2 sm = L.val[h];
-        L.tag[h] = kEmptyPid;
-        L.val[h].rg = 0;
-        L.val[h].ba = 0;
-        gadd_u64(S + 2 * (u64)pid, sm.rg);
-        gadd_u64(S + 2 * (u64)pid + 1, sm.ba);
-    }
+    flush_sum_pairs(L, S, cnt, wg);
     lds_barrier();
     par ^= 1u;
 }
