@@ -54,14 +54,14 @@ HBM_PEAK_GBS = 8000.0
 # `src` is the sha256 of the render sources.
 MEASURED_TRAFFIC = {
     # profiles/basic_dedup_796M_buildings_1080p.md (one dispatch each)
-    ("k_basic", 796_000_000): {"src": "f9549371e088cb468a814c45fb37c80ebd0e506e2de4e49ee186bebf5658d733",
+    ("k_basic", 796_000_000): {"src": "ff82f82c3c3becc0581d5b8b3b483e7ec2fd0022ca57b9fefe3e526737b655bd",
                                 "fetch_bytes": 8423712 * 2048, "write_bytes": 23437392 * 1024},
-    ("k_dedup<u64>", 796_000_000): {"src": "f9549371e088cb468a814c45fb37c80ebd0e506e2de4e49ee186bebf5658d733",
+    ("k_dedup<u64>", 796_000_000): {"src": "ff82f82c3c3becc0581d5b8b3b483e7ec2fd0022ca57b9fefe3e526737b655bd",
                                      "fetch_bytes": 6218804 * 2048, "write_bytes": 355971 * 1024},
     # profiles/render_terrain100M_1080p.md (averaged over the three orders)
-    ("k_basic", 100_000_000): {"src": "f9549371e088cb468a814c45fb37c80ebd0e506e2de4e49ee186bebf5658d733",
+    ("k_basic", 100_000_000): {"src": "ff82f82c3c3becc0581d5b8b3b483e7ec2fd0022ca57b9fefe3e526737b655bd",
                                 "fetch_bytes": 889979 * 2048, "write_bytes": 1034719 * 1024},
-    ("k_dedup<u64>", 100_000_000): {"src": "f9549371e088cb468a814c45fb37c80ebd0e506e2de4e49ee186bebf5658d733",
+    ("k_dedup<u64>", 100_000_000): {"src": "ff82f82c3c3becc0581d5b8b3b483e7ec2fd0022ca57b9fefe3e526737b655bd",
                                      "fetch_bytes": 781303 * 2048, "write_bytes": 106438 * 1024},
 }
 

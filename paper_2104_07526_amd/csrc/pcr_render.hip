@@ -691,7 +691,7 @@ __device__ __forceinline__ void flush_sum_pairs(Lds<Sum2> &L, u64 *__restrict__ 
     for (uint32_t k2 = threadIdx.x; k2 < 2 * cnt; k2 += wg) {
         const uint32_t h = L.list[k2 >> 1], half = k2 & 1u;
         const uint32_t pid = L.tag[h];
-        u64 *word = &L.val[h].rg + half;  // rg, then ba
+        u64 *word = half ? &L.val[h].ba : &L.val[h].rg;
         const u64 x = *word;
         *word = 0;
         if (!half) L.tag[h] = kEmptyPid;
