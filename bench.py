@@ -178,6 +178,31 @@ def cpu_baseline(pts, m, W, H, frames_per_step, what, target_s=12.0):
             "host": host_info()}
 
 
+def read_probe_rate(buf, reps=5):
+    """Rate of the read probe over the resident tensor ``buf`` (GB/s, median
+    of `reps` timed launches, the faster of two launch shapes), and its
+    average launch time in ms."""
+    import torch
+    from paper_2104_07526_amd import pcr
+    sink = torch.zeros(1, dtype=torch.int32, device=buf.device)
+    best = None
+    for per_thread, wgs in ((4, 4096), (8, 2048)):
+        pcr.probe_read(buf, per_thread, wgs, sink)   # warm-up
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            nbytes = pcr.probe_read(buf, per_thread, wgs, sink)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        r = {"GB_s": round(nbytes / (float(np.median(ms)) * 1e-3) / 1e9, 1), "ms": round(float(np.median(ms)), 4),
+             "per_thread": per_thread, "workgroups": wgs, "bytes": nbytes}
+        if best is None or r["GB_s"] > best["GB_s"]:
+            best = r
+    return best
+
+
 def probe_rate(pattern, words, returning=False, reps=3):
     """Device-wide atomicMin rate of one probe pattern (G atomics/s, median of
     `reps` launches timed with HIP events on the current stream)."""
@@ -333,6 +358,9 @@ def leg_main(args):
     words = W * H // 64 * 64
     probe = {name: round(probe_rate(p, words), 2) for name, p in PROBE_PATTERNS.items()}
     atom_rate = visible / (kms["basic"] * 1e-3) / 1e9
+    # The practical floor of the point stream: the same buffer read once with
+    # nothing else done (the deduplicating kernel's access pattern).
+    read = read_probe_rate(d)
     # HQ frame of the same cloud (two passes over the points)
     fbh = pcr.alloc_fb(W, H, pcr.HQ)
     hq_timer = Timer()
@@ -389,7 +417,10 @@ def leg_main(args):
                    "roofline_" + other: {"bound": "hbm", "kernel": kname[other], "achieved": round(o_ach, 1),
                                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                          "frac": round(o_ach / HBM_PEAK_GBS, 4),
-                                         "traffic": traffic_for(kname[other], n), "avg_ms": round(kms[other], 4)},
+                                         "traffic": traffic_for(kname[other], n), "avg_ms": round(kms[other], 4),
+                                         "frac_of_read_probe": round(o_ach / read["GB_s"], 4)},
+                   "read_probe": {**read, "note": "the cloud's buffer read once by pcr_probe_read (non-temporal "
+                                                  "16-byte loads, no other work): the practical floor of a frame"},
                    "hq_frame": hq,
                    "atomic_probe_G_per_s": {**probe, "footprint_MB": round(8 * words / 1e6, 2)},
                    "reorder_ms": round(rms, 2),

@@ -436,6 +436,23 @@ enum {
 int pcr_probe_atomics(unsigned long long *buf, uint64_t words, int pattern, int returning, uint32_t workgroups,
                       uint32_t iters, uint32_t seed, unsigned long long *sink, void *stream);
 
+/* Read-rate probe: streams the n16 16-byte records of buf once, in the
+ * access pattern of the render kernels' point loads (non-temporal 16-byte
+ * loads, workgroup tiles of per_thread * 256 records, grid-stride over the
+ * tiles), and does nothing else with them, so that timing the call gives the
+ * rate at which the chip delivers a point buffer (the floor of a frame of the
+ * deduplicating renderers, Sec. 3.4, whose point stream is their only HBM
+ * traffic).
+ *   buf         device, 16-byte aligned, 16 * n16 bytes, only read
+ *   per_thread  4 or 8 records per lane and tile
+ *   workgroups  in [1, 2^22], of 256 threads
+ *   sink        device uint32, 4-byte aligned; a lane stores the XOR of its
+ *               records there when it equals one fixed value (so that every
+ *               loaded value is consumed): its content means nothing
+ * n16 = 0 is a no-op.  Errors: PCR_EINVAL for bad pointers or sizes. */
+int pcr_probe_read(const void *buf, uint64_t n16, uint32_t per_thread, uint32_t workgroups, uint32_t *sink,
+                   void *stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *pcr_last_error(void);
 

@@ -1,7 +1,8 @@
 // pcr_probe.hip -- measurement helpers: the number of points a view keeps
-// (one global atomic each in the basic renderer of Sec. 3.1), and a
+// (one global atomic each in the basic renderer of Sec. 3.1), a
 // microbenchmark of device-wide 64-bit atomic minimum throughput, the rate
-// that bounds that renderer on this chip.
+// that bounds that renderer on this chip, and a read-only stream of a point
+// buffer, the practical floor of the deduplicating renderers' point stream.
 #include "pcr_internal.h"
 
 namespace pcr {
@@ -74,6 +75,31 @@ __global__ __launch_bounds__(256) void k_probe_atomics(u64 *__restrict__ buf, ui
     if (RET && acc == 0x5A5A5A5A5A5A5A5Aull) sink[0] = acc;
 }
 
+// Read-only stream of n 16-byte records in the render kernels' access
+// pattern (workgroup tiles of U * 256 records, record j * 256 + thread of a
+// tile in row j, non-temporal loads, grid-stride over the tiles): the rate at
+// which this chip delivers a point buffer with no other work.  The records are
+// folded into one word per lane, stored only if it takes one fixed value (the
+// stored word means nothing), so every load must complete.
+template <int U>
+__global__ __launch_bounds__(256) void k_probe_read(const u32x4 *__restrict__ p, uint64_t n,
+                                                    uint32_t *__restrict__ sink) {
+    const uint64_t ntiles = (n + U * 256ull - 1) / (U * 256ull);
+    uint32_t acc = 0;
+#pragma unroll 1
+    for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        u32x4 v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint64_t i = t * (U * 256ull) + j * 256u + threadIdx.x;
+            v[j] = load_point(p + (i < n ? i : n - 1));
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) acc ^= (v[j].x ^ v[j].y) ^ (v[j].z ^ v[j].w);
+    }
+    if (acc == 0x5A5A5A5Au) sink[0] = acc;
+}
+
 }  // namespace pcr
 
 using namespace pcr;
@@ -122,6 +148,23 @@ extern "C" int pcr_probe_atomics(unsigned long long *buf, uint64_t words, int pa
         default: return fail(PCR_EINVAL, "unknown probe pattern %d", pattern);
     }
 #undef PCR_PR
+    PCR_LAUNCHED();
+    return PCR_OK;
+}
+
+extern "C" int pcr_probe_read(const void *buf, uint64_t n16, uint32_t per_thread, uint32_t workgroups,
+                              uint32_t *sink, void *stream) {
+    if (n16 == 0) return PCR_OK;
+    if (!buf || ((uintptr_t)buf & 15)) return fail(PCR_EINVAL, "buf must be a 16-byte aligned device pointer");
+    if (per_thread != 4 && per_thread != 8) return fail(PCR_EINVAL, "per_thread must be 4 or 8 (got %u)", per_thread);
+    if (workgroups == 0 || workgroups > (1u << 22)) return fail(PCR_EINVAL, "workgroups must be in [1, 2^22]");
+    if (!sink || ((uintptr_t)sink & 3)) return fail(PCR_EINVAL, "sink must be a 4-byte aligned device pointer");
+    hipStream_t s = (hipStream_t)stream;
+    const u32x4 *p = (const u32x4 *)buf;
+    if (per_thread == 4)
+        hipLaunchKernelGGL(k_probe_read<4>, dim3(workgroups), dim3(256), 0, s, p, n16, sink);
+    else
+        hipLaunchKernelGGL(k_probe_read<8>, dim3(workgroups), dim3(256), 0, s, p, n16, sink);
     PCR_LAUNCHED();
     return PCR_OK;
 }

@@ -82,6 +82,7 @@ def _declare(lib):
         "pcr_check_reciprocal": (I32, [U32, U32, P, P]),
         "pcr_count_visible": (I32, [P, U64, P, U32, U32, P, P]),
         "pcr_probe_atomics": (I32, [P, U64, I32, I32, U32, U32, U32, P, P]),
+        "pcr_probe_read": (I32, [P, U64, U32, U32, P, P]),
         "pcr_last_error": (ctypes.c_char_p, []),
         "pcr_version": (ctypes.c_char_p, []),
     }
@@ -207,6 +208,19 @@ def probe_atomics(buf, pattern, returning=False, workgroups=8192, iters=64, seed
     _check(lib().pcr_probe_atomics(_ptr(buf), words, pattern, int(bool(returning)), workgroups, iters, seed,
                                    _ptr(sink), _stream(stream)))
     return workgroups * 256 * iters
+
+
+def probe_read(buf, per_thread=4, workgroups=4096, sink=None, stream=None):
+    """Enqueues the read-rate probe over the tensor ``buf`` (its bytes taken
+    as 16-byte records; a partial last record is left out).  ``sink``: an
+    int32 device tensor (allocated if None).  Returns the bytes it reads."""
+    import torch
+    n16 = buf.numel() * buf.element_size() // 16
+    if sink is None:
+        sink = torch.zeros(1, dtype=torch.int32, device=buf.device)
+    _fits(sink, 4, "sink")
+    _check(lib().pcr_probe_read(_ptr(buf), n16, per_thread, workgroups, _ptr(sink), _stream(stream)))
+    return 16 * n16
 
 
 def fb_bytes(w, h, variant) -> int:

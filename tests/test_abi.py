@@ -216,8 +216,8 @@ def test_binding_checks_tensor_sizes_before_enqueueing():
 
 
 def test_measurement_helpers_check_arguments():
-    """pcr_count_visible and pcr_probe_atomics refuse bad arguments on the
-    host (no GPU call is made for them)."""
+    """pcr_count_visible, pcr_probe_atomics and pcr_probe_read refuse bad
+    arguments on the host (no GPU call is made for them)."""
     L = pcr.lib()
     m = (ctypes.c_float * 16)()
     assert L.pcr_count_visible(None, 0, m, 0, 4, 8, None) == pcr.EINVAL
@@ -231,6 +231,15 @@ def test_measurement_helpers_check_arguments():
     assert L.pcr_probe_atomics(64, 64, 4, 0, 1, 1, 0, None, None) == pcr.EINVAL   # unknown pattern
     assert L.pcr_probe_atomics(64, 64, 0, 1, 1, 1, 0, None, None) == pcr.EINVAL   # returning without sink
     assert L.pcr_probe_atomics(64, 64, 0, 0, 0, 1, 0, None, None) == pcr.EINVAL   # no workgroups
+    assert L.pcr_probe_read(None, 0, 4, 1, None, None) == pcr.OK                   # n16 == 0: nothing to do
+    assert L.pcr_probe_read(None, 4, 4, 1, 64, None) == pcr.EINVAL                 # no buffer
+    assert L.pcr_probe_read(72, 4, 4, 1, 64, None) == pcr.EINVAL                   # misaligned buffer
+    for per_thread in (0, 1, 2, 16):
+        assert L.pcr_probe_read(64, 4, per_thread, 1, 64, None) == pcr.EINVAL
+    for wgs in (0, (1 << 22) + 1):
+        assert L.pcr_probe_read(64, 4, 4, wgs, 64, None) == pcr.EINVAL
+    assert L.pcr_probe_read(64, 4, 4, 1, None, None) == pcr.EINVAL                 # no sink
+    assert L.pcr_probe_read(64, 4, 4, 1, 66, None) == pcr.EINVAL                   # misaligned sink
 
 
 def test_static_chunks_refuse_too_many_chunks():
